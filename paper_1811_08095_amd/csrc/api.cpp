@@ -1,0 +1,400 @@
+// C ABI of libodwf: lattices, solvers, operator application and the
+// even-odd preconditioned CG solves (FP64, FP32 with FP64 reliable updates,
+// FP16/BF16 storage with FP64 defect correction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+#include "solver.h"
+
+using namespace odwf;
+
+namespace odwf {
+const char* last_error_cstr();
+void prof_enable(int on);
+void prof_read(long long* launches, double* ms, double* bytes);
+}  // namespace odwf
+
+#define HIPCHK(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+      return ODWF_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+#define REQUIRE(cond, msg)       \
+  do {                           \
+    if (!(cond)) {               \
+      set_error(msg);            \
+      return ODWF_EINVAL;        \
+    }                            \
+  } while (0)
+
+static bool ns_supported(int Ns) { return Ns == 4 || Ns == 8 || Ns == 16 || Ns == 32; }
+
+// ------------------------------------------------------------------------------
+// lattices
+// ------------------------------------------------------------------------------
+
+extern "C" odwf_status odwf_lattice_create(const int dims[4], int bc_t, int device,
+                                           odwf_lattice* out) {
+  REQUIRE(dims && out, "odwf_lattice_create: null argument");
+  for (int d = 0; d < 4; d++)
+    REQUIRE(dims[d] >= 2 && dims[d] % 2 == 0 && dims[d] <= 4096,
+            "odwf_lattice_create: every extent must be even, >= 2 and <= 4096");
+  REQUIRE(bc_t == 1 || bc_t == -1, "odwf_lattice_create: bc_t must be +1 or -1");
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  REQUIRE(V / 2 <= (1L << 30), "odwf_lattice_create: lattice too large");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  REQUIRE(device >= 0 && device < ndev, "odwf_lattice_create: bad device index");
+  HIPCHK(hipSetDevice(device));
+  odwf_lattice L = new odwf_lattice_s();
+  for (int d = 0; d < 4; d++) {
+    L->dims[d] = dims[d];
+    L->g.L[d] = dims[d];
+  }
+  L->bc_t = bc_t;
+  L->device = device;
+  L->g.V = V;
+  L->g.h = V / 2;
+  *out = L;
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_lattice_load_gauge(odwf_lattice L, const void* U, int on_device,
+                                               void* stream) {
+  REQUIRE(L && U, "odwf_lattice_load_gauge: null argument");
+  HIPCHK(hipSetDevice(L->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t canon_bytes = (size_t)L->g.V * 4 * 9 * 16;
+  const void* src = U;
+  void* tmp = nullptr;
+  if (!on_device) {
+    if (hipMalloc(&tmp, canon_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("odwf_lattice_load_gauge: out of device memory for staging");
+      return ODWF_ENOMEM;
+    }
+    HIPCHK(hipMemcpyAsync(tmp, U, canon_bytes, hipMemcpyHostToDevice, st));
+    src = tmp;
+  }
+  const size_t b64 = (size_t)L->g.h * 8 * 18 * sizeof(double);
+  const size_t b32 = (size_t)L->g.h * 8 * 12 * sizeof(float);
+  for (int p = 0; p < 2; p++) {
+    if (!L->U64[p] && hipMalloc(&L->U64[p], b64) != hipSuccess) {
+      (void)hipGetLastError();
+      L->U64[p] = nullptr;
+      if (tmp) (void)hipFree(tmp);
+      set_error("odwf_lattice_load_gauge: out of device memory");
+      return ODWF_ENOMEM;
+    }
+    if (!L->U32[p] && hipMalloc(&L->U32[p], b32) != hipSuccess) {
+      (void)hipGetLastError();
+      L->U32[p] = nullptr;
+      if (tmp) (void)hipFree(tmp);
+      set_error("odwf_lattice_load_gauge: out of device memory");
+      return ODWF_ENOMEM;
+    }
+    HIPCHK(launch_pack_gauge(src, L->U64[p], p, PREC64, L->g, st));
+    HIPCHK(launch_pack_gauge(src, L->U32[p], p, PREC32, L->g, st));
+  }
+  if (tmp) {
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(tmp));
+  }
+  L->loaded = true;
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_lattice_bytes(odwf_lattice L, size_t* bytes) {
+  REQUIRE(L && bytes, "odwf_lattice_bytes: null argument");
+  *bytes = (L->U64[0] ? 2 * (size_t)L->g.h * 8 * 18 * sizeof(double) : 0) +
+           (L->U32[0] ? 2 * (size_t)L->g.h * 8 * 12 * sizeof(float) : 0);
+  return ODWF_OK;
+}
+
+extern "C" void odwf_lattice_destroy(odwf_lattice L) {
+  if (!L) return;
+  (void)hipSetDevice(L->device);
+  for (int p = 0; p < 2; p++) {
+    if (L->U64[p]) (void)hipFree(L->U64[p]);
+    if (L->U32[p]) (void)hipFree(L->U32[p]);
+  }
+  delete L;
+}
+
+// ------------------------------------------------------------------------------
+// solvers
+// ------------------------------------------------------------------------------
+
+extern "C" odwf_status odwf_solver_create(odwf_lattice L, int Ns, double m0, const double* omega,
+                                          odwf_solver* out) {
+  REQUIRE(L && omega && out, "odwf_solver_create: null argument");
+  REQUIRE(ns_supported(Ns), "odwf_solver_create: Ns must be 4, 8, 16 or 32");
+  REQUIRE(std::isfinite(m0), "odwf_solver_create: m0 must be finite");
+  for (int s = 0; s < Ns; s++)
+    REQUIRE(std::isfinite(omega[s]) && omega[s] > 0, "odwf_solver_create: omega_s must be > 0");
+  HIPCHK(hipSetDevice(L->device));
+  odwf_solver S = new odwf_solver_s();
+  S->lat = L;
+  S->Ns = Ns;
+  S->m0 = m0;
+  S->omega.assign(omega, omega + Ns);
+  // coefficient table [chi][id][q], chirality - in mirrored order
+  std::vector<double> c64(2 * NCOEF * Ns);
+  std::vector<float> c32(2 * NCOEF * Ns);
+  const double k4 = 4.0 - m0;
+  for (int chi = 0; chi < 2; chi++) {
+    auto w = [&](int q) { return omega[chi ? Ns - 1 - q : q]; };
+    for (int q = 0; q < Ns; q++) {
+      const double a = k4 * w(q) + 1.0, c = k4 * w(q) - 1.0;
+      const double cn = k4 * w(q + 1 < Ns ? q + 1 : 0) - 1.0;
+      double v[NCOEF];
+      v[CF_ONE] = 1.0;
+      v[CF_MONE] = -1.0;
+      v[CF_OMEGA] = w(q);
+      v[CF_OMEGA_INV] = 1.0 / w(q);
+      v[CF_A] = a;
+      v[CF_A_INV] = 1.0 / a;
+      v[CF_C] = c;
+      v[CF_CSHIFT] = cn;
+      for (int id = 0; id < NCOEF; id++) {
+        c64[(chi * NCOEF + id) * Ns + q] = v[id];
+        c32[(chi * NCOEF + id) * Ns + q] = (float)v[id];
+      }
+    }
+  }
+  if (hipMalloc(&S->coef64, c64.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&S->coef32, c32.size() * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete S;
+    set_error("odwf_solver_create: out of device memory");
+    return ODWF_ENOMEM;
+  }
+  HIPCHK(hipMemcpy(S->coef64, c64.data(), c64.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(S->coef32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  *out = S;
+  return ODWF_OK;
+}
+
+extern "C" void odwf_solver_destroy(odwf_solver S) {
+  if (!S) return;
+  (void)hipSetDevice(S->lat->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : S->ws) delete kv.second;
+  if (S->coef64) (void)hipFree(S->coef64);
+  if (S->coef32) (void)hipFree(S->coef32);
+  delete S;
+}
+
+// ------------------------------------------------------------------------------
+// operator application
+// ------------------------------------------------------------------------------
+
+static odwf_status apply_chunk(odwf_solver S, odwf_op op, const double* mq, int prec, int r0,
+                               int nrhs, const void* in, void* out, hipStream_t st) {
+  Workspace& W = S->workspace(st);
+  const Geom& g = S->lat->g;
+  const int Ns = S->Ns;
+  OpCtx c;
+  c.S = S;
+  c.st = st;
+  c.prec = prec;
+  c.nrhs = nrhs;
+  for (int r = 0; r < MAXRHS; r++) c.kappa[r] = r < nrhs ? -mq[r0 + r] / (2.0 * S->m0) : 0.0;
+  HV ie = W.half("ap.ie", g.h, nrhs, Ns, prec), io = W.half("ap.io", g.h, nrhs, Ns, prec);
+  HV oe = W.half("ap.oe", g.h, nrhs, Ns, prec), oo = W.half("ap.oo", g.h, nrhs, Ns, prec);
+  HV te = W.half("ap.te", g.h, nrhs, Ns, prec), to = W.half("ap.to", g.h, nrhs, Ns, prec);
+  if (!ie.d || !io.d || !oe.d || !oo.d || !te.d || !to.d) {
+    set_error("odwf_apply: out of device memory for workspaces");
+    return ODWF_ENOMEM;
+  }
+  HIPCHK(launch_pack_spinor(prec, in, r0, ie.d, ie.sc, 0, nrhs, Ns, g, st));
+  HIPCHK(launch_pack_spinor(prec, in, r0, io.d, io.sc, 1, nrhs, Ns, g, st));
+  bool have_e = true, have_o = true;
+  HopOpt o;
+  switch (op) {
+    case ODWF_OP_HOP_EO:
+      HIPCHK(hop(c, 0, 0, io, &oe, o));
+      have_o = false;
+      break;
+    case ODWF_OP_HOP_OE:
+      HIPCHK(hop(c, 1, 0, ie, &oo, o));
+      have_e = false;
+      break;
+    case ODWF_OP_M5INV:
+      HIPCHK(m5(c, ie, oe, prog_ainv()));
+      HIPCHK(m5(c, io, oo, prog_ainv()));
+      break;
+    case ODWF_OP_D:
+    case ODWF_OP_DDAGD:
+      HIPCHK(apply_D(c, ie, io, te, to, oe, oo));
+      if (op == ODWF_OP_DDAGD) {
+        HIPCHK(apply_Ddag(c, oe, oo, te, to, ie, io));
+        std::swap(oe, ie);
+        std::swap(oo, io);
+      }
+      break;
+    case ODWF_OP_DDAG:
+      HIPCHK(apply_Ddag(c, ie, io, te, to, oe, oo));
+      break;
+    case ODWF_OP_SCHUR:
+      HIPCHK(apply_schur(c, ie, to, oe));
+      have_o = false;
+      break;
+    case ODWF_OP_SCHUR_DAG:
+      HIPCHK(apply_schur_dag(c, ie, te, to, oe));
+      have_o = false;
+      break;
+    case ODWF_OP_SCHUR_NORMAL:
+      HIPCHK(apply_normal(c, ie, to, te, oe, nullptr));
+      have_o = false;
+      break;
+    default:
+      set_error("odwf_apply: unknown operator");
+      return ODWF_EINVAL;
+  }
+  if (have_e) HIPCHK(launch_unpack_spinor(prec, oe.d, oe.sc, out, r0, 0, nrhs, Ns, g, st));
+  else HIPCHK(launch_zero_canon_parity(out, r0, 0, nrhs, Ns, g, st));
+  if (have_o) HIPCHK(launch_unpack_spinor(prec, oo.d, oo.sc, out, r0, 1, nrhs, Ns, g, st));
+  else HIPCHK(launch_zero_canon_parity(out, r0, 1, nrhs, Ns, g, st));
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_apply(odwf_solver S, odwf_op op, const double* mq, odwf_prec prec,
+                                  int nrhs, const void* in, void* out, void* stream) {
+  REQUIRE(S && mq && in && out, "odwf_apply: null argument");
+  REQUIRE(nrhs >= 1, "odwf_apply: nrhs must be >= 1");
+  REQUIRE(in != out, "odwf_apply: in and out must be distinct buffers");
+  REQUIRE(prec >= ODWF_FP64 && prec <= ODWF_BF16S, "odwf_apply: bad precision");
+  REQUIRE(S->lat->loaded, "odwf_apply: gauge field not loaded");
+  for (int r = 0; r < nrhs; r++) REQUIRE(std::isfinite(mq[r]), "odwf_apply: mq must be finite");
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  const int chunk = max_rhs_per_launch(S->Ns);
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int n = std::min(chunk, nrhs - r0);
+    odwf_status s = apply_chunk(S, op, mq, (int)prec, r0, n, in, out, st);
+    if (s != ODWF_OK) return s;
+  }
+  return ODWF_OK;
+}
+
+// ------------------------------------------------------------------------------
+// solves
+// ------------------------------------------------------------------------------
+
+extern "C" odwf_status odwf_solve(odwf_solver S, odwf_mode mode, const double* mq, const double* tol,
+                                  int nrhs, odwf_prec inner, int maxiter, const void* b, void* x,
+                                  int use_x0, odwf_stats* stats, void* stream) {
+  REQUIRE(S && mq && tol && b && x, "odwf_solve: null argument");
+  REQUIRE(nrhs >= 1, "odwf_solve: nrhs must be >= 1");
+  REQUIRE(mode == ODWF_SOLVE_EO_NORMAL || mode == ODWF_SOLVE_FULL, "odwf_solve: bad mode");
+  REQUIRE(inner >= ODWF_FP64 && inner <= ODWF_BF16S, "odwf_solve: bad inner precision");
+  REQUIRE(maxiter >= 1, "odwf_solve: maxiter must be >= 1");
+  REQUIRE(!(use_x0 && b == x), "odwf_solve: x may alias b only when use_x0 == 0");
+  REQUIRE(S->lat->loaded, "odwf_solve: gauge field not loaded");
+  for (int r = 0; r < nrhs; r++) {
+    REQUIRE(std::isfinite(mq[r]), "odwf_solve: mq must be finite");
+    REQUIRE(tol[r] > 0 && tol[r] < 1, "odwf_solve: tol must be in (0, 1)");
+  }
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  odwf_status worst = ODWF_OK;
+  const int chunk = max_rhs_per_launch(S->Ns);
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int n = std::min(chunk, nrhs - r0);
+    odwf_status s = solve_chunk(S, (int)mode, mq + r0, tol + r0, r0, n, (int)inner, maxiter, b, x,
+                                use_x0, stats ? stats + r0 : nullptr, st);
+    if (s == ODWF_EHIP || s == ODWF_ENOMEM || s == ODWF_EINVAL) return s;
+    if (s != ODWF_OK && worst == ODWF_OK) worst = s;
+  }
+  return worst;
+}
+
+extern "C" odwf_status odwf_footprint(const int dims[4], int Ns, int nrhs, odwf_prec inner,
+                                      size_t* bytes) {
+  REQUIRE(dims && bytes, "odwf_footprint: null argument");
+  REQUIRE(ns_supported(Ns) && nrhs >= 1, "odwf_footprint: bad Ns or nrhs");
+  const long h = (long)dims[0] * dims[1] * dims[2] * dims[3] / 2;
+  *bytes = solve_workspace_bytes(h, Ns, std::min(nrhs, max_rhs_per_launch(Ns)), (int)inner);
+  return ODWF_OK;
+}
+
+// ------------------------------------------------------------------------------
+// optimal weights
+// ------------------------------------------------------------------------------
+
+// Jacobi amplitude by the arithmetic-geometric mean and descending Landen
+// transformation (Abramowitz & Stegun 16.4): returns dn(u | m) and K(m).
+static void jacobi_dn_K(double u, double m, double* dn, double* K) {
+  double a[64], c[64];
+  a[0] = 1.0;
+  double b = std::sqrt(1.0 - m);
+  c[0] = std::sqrt(m);
+  int n = 0;
+  while (std::fabs(c[n]) > 1e-17 && n < 60) {
+    a[n + 1] = 0.5 * (a[n] + b);
+    c[n + 1] = 0.5 * (a[n] - b);
+    b = std::sqrt(a[n] * b);
+    n++;
+  }
+  *K = M_PI / (2.0 * a[n]);
+  double phi = std::ldexp(1.0, n) * a[n] * u;
+  double phi_prev = phi;
+  for (int k = n; k >= 1; k--) {
+    phi_prev = phi;
+    phi = 0.5 * (phi + std::asin(c[k] / a[k] * std::sin(phi)));
+  }
+  // dn = cos(phi0) / cos(phi1 - phi0)
+  *dn = n >= 1 ? std::cos(phi) / std::cos(phi_prev - phi) : 1.0;
+}
+
+extern "C" odwf_status odwf_zolotarev_omega(int Ns, double lmin, double lmax, double* omega) {
+  REQUIRE(omega, "odwf_zolotarev_omega: null argument");
+  REQUIRE(Ns >= 2 && Ns % 2 == 0, "odwf_zolotarev_omega: Ns must be even and >= 2");
+  REQUIRE(lmin > 0 && lmax > lmin, "odwf_zolotarev_omega: need 0 < lambda_min < lambda_max");
+  const double m = 1.0 - (lmin / lmax) * (lmin / lmax);
+  double dn, K;
+  jacobi_dn_K(0.0, m, &dn, &K);
+  std::vector<double> half(Ns / 2);
+  for (int k = 1; k <= Ns / 2; k++) {
+    jacobi_dn_K((2 * k - 1) * K / Ns, m, &dn, &K);
+    half[k - 1] = dn / lmin;
+  }
+  std::sort(half.begin(), half.end(), [](double p, double q) { return p > q; });
+  for (int k = 0; k < Ns / 2; k++) {
+    omega[k] = half[k];
+    omega[Ns - 1 - k] = half[k];
+  }
+  return ODWF_OK;
+}
+
+// ------------------------------------------------------------------------------
+// profiling and errors
+// ------------------------------------------------------------------------------
+
+extern "C" odwf_status odwf_profile_enable(int enable) {
+  prof_enable(enable);
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_profile_read(long long* launches, double* ms, double* bytes) {
+  prof_read(launches, ms, bytes);
+  return ODWF_OK;
+}
+
+extern "C" const char* odwf_last_error(void) { return last_error_cstr(); }
+
+extern "C" const char* odwf_version(void) { return "odwf-mi355x 0.1 (gfx950)"; }

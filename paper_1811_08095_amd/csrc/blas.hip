@@ -1,0 +1,259 @@
+// BLAS-1 kernels on even/odd half fields and the CG scalar finalisation.
+//
+// Threads map to 5D sites (j, r, s) with s fastest and a block size that is a
+// multiple of nrhs * Ns, so every thread keeps one right-hand side across its
+// grid-stride loop and per-right-hand-side reductions stay deterministic:
+// per-block partial sums (fixed order) followed by a one-block finalisation
+// that sums the partials in a fixed tree.  All accumulations are FP64.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace odwf {
+
+static inline int vec_spb(int nrhs, int Ns) {
+  const int inner = nrhs * Ns;
+  return inner >= 256 ? 1 : 256 / inner;
+}
+
+int vec_nblocks(long h, int nrhs, int Ns) {
+  const int spb = vec_spb(nrhs, Ns);
+  long nb = (h + spb - 1) / spb;
+  if (nb > 2048) nb = 2048;
+  return (int)nb;
+}
+
+template <class P>
+__global__ void vec_zero_kernel(void* v, float* sc, long h, int nrhs, int Ns) {
+  using R = typename P::real;
+  const int inner = nrhs * Ns;
+  const int spb = blockDim.x / inner;
+  const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
+  cpx<R> z[12];
+#pragma unroll
+  for (int c = 0; c < 12; c++) z[c] = {R(0), R(0)};
+  for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb)
+    store_site<P>(v, sc, j, r, s, nrhs, Ns, z);
+}
+
+template <class PS, class PD>
+__global__ void vec_convert_kernel(const void* src, const float* src_sc, void* dst, float* dst_sc,
+                                   int accumulate, const int* rhs_mask, long h, int nrhs, int Ns) {
+  using RS = typename PS::real;
+  using RD = typename PD::real;
+  const int inner = nrhs * Ns;
+  const int spb = blockDim.x / inner;
+  const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
+  if (rhs_mask && !rhs_mask[r]) return;
+  for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb) {
+    cpx<RS> a[12];
+    load_site<PS>(src, src_sc, j, r, s, nrhs, Ns, a);
+    cpx<RD> b[12];
+    if (accumulate) {
+      load_site<PD>(dst, dst_sc, j, r, s, nrhs, Ns, b);
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c] = {b[c].re + (RD)a[c].re, b[c].im + (RD)a[c].im};
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c] = {(RD)a[c].re, (RD)a[c].im};
+    }
+    store_site<PD>(dst, dst_sc, j, r, s, nrhs, Ns, b);
+  }
+}
+
+template <class P>
+__global__ void vec_xpby_kernel(const void* x, const float* x_sc, void* y, float* y_sc,
+                                const CGScal* scal, long h, int nrhs, int Ns) {
+  using R = typename P::real;
+  const int inner = nrhs * Ns;
+  const int spb = blockDim.x / inner;
+  const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
+  if (!scal[r].active) return;
+  const R beta = (R)scal[r].beta;
+  for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb) {
+    cpx<R> a[12], b[12];
+    load_site<P>(x, x_sc, j, r, s, nrhs, Ns, a);
+    load_site<P>(y, y_sc, j, r, s, nrhs, Ns, b);
+#pragma unroll
+    for (int c = 0; c < 12; c++) b[c] = cadd(a[c], cscale(beta, b[c]));
+    store_site<P>(y, y_sc, j, r, s, nrhs, Ns, b);
+  }
+}
+
+template <class P>
+__global__ void vec_norm2_kernel(const void* v, const float* sc, double* partial, long h, int nrhs,
+                                 int Ns) {
+  using R = typename P::real;
+  __shared__ double red[1024 + 16 * MAXRHS];
+  const int inner = nrhs * Ns;
+  const int spb = blockDim.x / inner;
+  const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
+  double acc = 0.0;
+  if (sl < spb)
+    for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb) {
+      cpx<R> a[12];
+      load_site<P>(v, sc, j, r, s, nrhs, Ns, a);
+#pragma unroll
+      for (int c = 0; c < 12; c++) acc += (double)cnorm2(a[c]);
+    }
+  red[threadIdx.x] = acc;
+  block_reduce_rhs(
+      red, blockDim.x, nrhs, [&](int k) { return (k % inner) / Ns; }, red + 1024, partial);
+}
+
+#define ODWF_PREC_SWITCH(prec, KERNEL, ...)                                             \
+  switch (prec) {                                                                       \
+    case PREC64: hipLaunchKernelGGL(KERNEL<SP64>, __VA_ARGS__); break;                  \
+    case PREC32: hipLaunchKernelGGL(KERNEL<SP32>, __VA_ARGS__); break;                  \
+    case PREC16: hipLaunchKernelGGL(KERNEL<SP16>, __VA_ARGS__); break;                  \
+    case PRECB16: hipLaunchKernelGGL(KERNEL<SPB16>, __VA_ARGS__); break;                \
+    default: return hipErrorInvalidValue;                                               \
+  }
+
+hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st) {
+  const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
+  const dim3 gr(vec_nblocks(h, nrhs, Ns));
+  ODWF_PREC_SWITCH(prec, vec_zero_kernel, gr, dim3(block), 0, st, v, sc, h, nrhs, Ns);
+  return hipGetLastError();
+}
+
+template <class PS>
+static hipError_t convert_to(int prec_dst, const void* src, const float* src_sc, void* dst,
+                             float* dst_sc, int acc, const int* mask, long h, int nrhs, int Ns,
+                             hipStream_t st) {
+  const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
+  const dim3 gr(vec_nblocks(h, nrhs, Ns));
+  switch (prec_dst) {
+    case PREC64: hipLaunchKernelGGL((vec_convert_kernel<PS, SP64>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
+    case PREC32: hipLaunchKernelGGL((vec_convert_kernel<PS, SP32>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
+    case PREC16: hipLaunchKernelGGL((vec_convert_kernel<PS, SP16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
+    case PRECB16: hipLaunchKernelGGL((vec_convert_kernel<PS, SPB16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc, int prec_dst,
+                              void* dst, float* dst_sc, int accumulate, const int* rhs_mask, long h,
+                              int nrhs, int Ns, hipStream_t st) {
+  switch (prec_src) {
+    case PREC64: return convert_to<SP64>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
+    case PREC32: return convert_to<SP32>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
+    case PREC16: return convert_to<SP16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
+    case PRECB16: return convert_to<SPB16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_vec_xpby(int prec, const void* x, const float* x_sc, void* y, float* y_sc,
+                           const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st) {
+  const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
+  const dim3 gr(vec_nblocks(h, nrhs, Ns));
+  ODWF_PREC_SWITCH(prec, vec_xpby_kernel, gr, dim3(block), 0, st, x, x_sc, y, y_sc, scal, h, nrhs, Ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_norm2(int prec, const void* v, const float* sc, double* partial, long h,
+                            int nrhs, int Ns, int* nblocks_out, hipStream_t st) {
+  const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
+  const int nb = vec_nblocks(h, nrhs, Ns);
+  if (nblocks_out) *nblocks_out = nb;
+  ODWF_PREC_SWITCH(prec, vec_norm2_kernel, dim3(nb), dim3(block), 0, st, v, sc, partial, h, nrhs, Ns);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finalisation: one block of 256 threads
+// ---------------------------------------------------------------------------
+__global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
+                           double* out) {
+  __shared__ double red[256];
+  __shared__ double sums[MAXRHS];
+  for (int r = 0; r < nrhs; r++) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partial[(long)b * nrhs + r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[r] = red[0];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x >= nrhs) return;
+  const int r = threadIdx.x;
+  const double v = sums[r];
+  if (out) out[r] = v;
+  if (!scal) return;
+  CGScal c = scal[r];
+  const bool finite = isfinite(v);
+  switch (kind) {
+    case FIN_F2:
+      c.f2 = v;
+      break;
+    case FIN_ALPHA:
+      c.pAp = v;
+      if (c.active) {
+        if (!finite || !(v > 0.0)) {
+          c.nan = !finite;
+          c.active = 0;
+          c.alpha = 0.0;
+        } else {
+          c.alpha = c.rr / v;
+        }
+      } else {
+        c.alpha = 0.0;
+      }
+      break;
+    case FIN_BETA:
+      if (c.active) {
+        c.iters += 1;
+        if (!finite) {
+          c.nan = 1;
+          c.active = 0;
+          c.beta = 0.0;
+        } else {
+          c.beta = v / c.rr;
+          c.rr = v;
+          if (v > c.rmax2) c.rmax2 = v;
+          if (v <= c.tol2 * c.f2) {
+            c.converged = 1;
+            c.active = 0;
+          } else if (c.iters >= c.maxiter) {
+            c.active = 0;
+          }
+          if (c.delta2 > 0.0 && v < c.delta2 * c.rmax2) c.update = 1;
+        }
+      } else {
+        c.beta = 0.0;
+      }
+      break;
+    case FIN_INIT:
+      // v = |r|^2 of a freshly computed true residual
+      c.rr = v;
+      c.rmax2 = v;
+      c.update = 0;
+      if (!finite) {
+        c.nan = 1;
+        c.active = 0;
+      } else if (v <= c.tol2 * c.f2) {
+        c.converged = 1;
+        c.active = 0;
+      } else {
+        c.converged = 0;
+        c.active = c.iters < c.maxiter ? 1 : 0;
+      }
+      break;
+    default:
+      break;
+  }
+  scal[r] = c;
+}
+
+hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
+                      double* out, hipStream_t st) {
+  hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, st, kind, partial, nblocks, nrhs, scal, out);
+  return hipGetLastError();
+}
+
+}  // namespace odwf

@@ -1,0 +1,359 @@
+// Device-side building blocks shared by the HIP kernels of libodwf:
+// complex arithmetic, spinor storage policies (FP64 / FP32 / FP16+scale /
+// BF16+scale), link formats, fifth-dimension programs and deterministic
+// per-right-hand-side block reductions.
+//
+// Internal spinor layout of one parity half (h = V/2 sites), per site j,
+// right-hand side r, fifth-dimension slice s and spin-colour component
+// c = spin*3 + colour (12 complex per 5D site):
+//     chunk (j, cg, r, s) of CPB consecutive complex numbers, cg = c / CPB,
+//     address = ((j * NCG + cg) * nrhs + r) * Ns + s   (in 16-byte chunks),
+// so the Ns * nrhs lanes of one site read consecutive 16-byte chunks.  The
+// reduced-precision formats keep one float scale per 5D site (j, r, s) at
+// (j * nrhs + r) * Ns + s; stored values are component / scale with scale the
+// largest |real| or |imag| part of the 24 reals.
+#pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "odwf_types.h"
+
+namespace odwf {
+
+template <class R>
+struct cpx {
+  R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ cpx<R> cscale(R f, cpx<R> a) { return {f * a.re, f * a.im}; }
+// a * b
+template <class R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <class R>
+__device__ __forceinline__ cpx<R> cfma(cpx<R> a, cpx<R> b, cpx<R> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// i * a
+template <class R>
+__device__ __forceinline__ cpx<R> cmuli(cpx<R> a) { return {-a.im, a.re}; }
+template <class R>
+__device__ __forceinline__ R cnorm2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// storage policies
+// ---------------------------------------------------------------------------
+
+struct SP64 {
+  using real = double;
+  static constexpr int CPB = 1;  // complex per 16-byte chunk
+  static constexpr bool SCALED = false;
+  static constexpr int BYTES = 16;  // bytes per complex
+};
+struct SP32 {
+  using real = float;
+  static constexpr int CPB = 2;
+  static constexpr bool SCALED = false;
+  static constexpr int BYTES = 8;
+};
+struct SP16 {
+  using real = float;
+  static constexpr int CPB = 4;
+  static constexpr bool SCALED = true;
+  static constexpr int BYTES = 4;
+};
+struct SPB16 {
+  using real = float;
+  static constexpr int CPB = 4;
+  static constexpr bool SCALED = true;
+  static constexpr int BYTES = 4;
+};
+
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+  // round to nearest even; inputs are finite and bounded by 1 after scaling
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// unpack one 16-byte chunk into CPB complex values
+template <class P>
+__device__ __forceinline__ void unpack_chunk(const uint4 q, cpx<typename P::real>* v);
+
+template <>
+__device__ __forceinline__ void unpack_chunk<SP64>(const uint4 q, cpx<double>* v) {
+  v[0].re = __hiloint2double((int)q.y, (int)q.x);
+  v[0].im = __hiloint2double((int)q.w, (int)q.z);
+}
+template <>
+__device__ __forceinline__ void unpack_chunk<SP32>(const uint4 q, cpx<float>* v) {
+  v[0] = {__uint_as_float(q.x), __uint_as_float(q.y)};
+  v[1] = {__uint_as_float(q.z), __uint_as_float(q.w)};
+}
+template <>
+__device__ __forceinline__ void unpack_chunk<SP16>(const uint4 q, cpx<float>* v) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    __half2 hh = *reinterpret_cast<const __half2*>(&w[k]);
+    float2 f = __half22float2(hh);
+    v[k] = {f.x, f.y};
+  }
+}
+template <>
+__device__ __forceinline__ void unpack_chunk<SPB16>(const uint4 q, cpx<float>* v) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int k = 0; k < 4; k++) v[k] = {bf16_to_f((uint16_t)(w[k] & 0xffffu)), bf16_to_f((uint16_t)(w[k] >> 16))};
+}
+
+template <class P>
+__device__ __forceinline__ uint4 pack_chunk(const cpx<typename P::real>* v, typename P::real inv);
+
+template <>
+__device__ __forceinline__ uint4 pack_chunk<SP64>(const cpx<double>* v, double) {
+  uint4 q;
+  q.x = (uint32_t)__double2loint(v[0].re);
+  q.y = (uint32_t)__double2hiint(v[0].re);
+  q.z = (uint32_t)__double2loint(v[0].im);
+  q.w = (uint32_t)__double2hiint(v[0].im);
+  return q;
+}
+template <>
+__device__ __forceinline__ uint4 pack_chunk<SP32>(const cpx<float>* v, float) {
+  return make_uint4(__float_as_uint(v[0].re), __float_as_uint(v[0].im), __float_as_uint(v[1].re),
+                    __float_as_uint(v[1].im));
+}
+template <>
+__device__ __forceinline__ uint4 pack_chunk<SP16>(const cpx<float>* v, float inv) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    __half2 hh = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
+    w[k] = *reinterpret_cast<uint32_t*>(&hh);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+template <>
+__device__ __forceinline__ uint4 pack_chunk<SPB16>(const cpx<float>* v, float inv) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    w[k] = (uint32_t)f_to_bf16(v[k].re * inv) | ((uint32_t)f_to_bf16(v[k].im * inv) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Spinor half-field view
+template <class P>
+struct HalfView {
+  const uint4* __restrict__ base;
+  const float* __restrict__ scale;
+};
+
+// load the 12 components of 5D site (j, r, s)
+template <class P>
+__device__ __forceinline__ void load_site(const void* base, const float* scale, long j, int r, int s,
+                                          int nrhs, int Ns, cpx<typename P::real> (&v)[12]) {
+  constexpr int NCG = 12 / P::CPB;
+  const uint4* b = reinterpret_cast<const uint4*>(base);
+  const long inner = (long)nrhs * Ns;
+  const long off = j * NCG * inner + (long)r * Ns + s;
+  uint4 q[NCG];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * inner];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
+  if constexpr (P::SCALED) {
+    float sc = scale[(j * nrhs + r) * Ns + s];
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = cscale(sc, v[c]);
+  }
+}
+
+// cached variant: for neighbour reads that other sites re-use
+template <class P>
+__device__ __forceinline__ void load_site_cached(const void* base, const float* scale, long j, int r,
+                                                 int s, int nrhs, int Ns,
+                                                 cpx<typename P::real> (&v)[12]) {
+  constexpr int NCG = 12 / P::CPB;
+  const uint4* b = reinterpret_cast<const uint4*>(base);
+  const long inner = (long)nrhs * Ns;
+  const long off = j * NCG * inner + (long)r * Ns + s;
+  uint4 q[NCG];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * inner];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
+  if constexpr (P::SCALED) {
+    float sc = scale[(j * nrhs + r) * Ns + s];
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = cscale(sc, v[c]);
+  }
+}
+
+template <class P>
+__device__ __forceinline__ void store_site(void* base, float* scale, long j, int r, int s, int nrhs,
+                                           int Ns, const cpx<typename P::real> (&v)[12]) {
+  using R = typename P::real;
+  constexpr int NCG = 12 / P::CPB;
+  uint4* b = reinterpret_cast<uint4*>(base);
+  const long inner = (long)nrhs * Ns;
+  const long off = j * NCG * inner + (long)r * Ns + s;
+  R inv = R(1);
+  if constexpr (P::SCALED) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; c++) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    scale[(j * nrhs + r) * Ns + s] = m;
+    inv = m > 0.f ? 1.0f / m : 0.f;
+  }
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) b[off + cg * inner] = pack_chunk<P>(&v[cg * P::CPB], inv);
+}
+
+// ---------------------------------------------------------------------------
+// fifth-dimension programs on one column y[0..NS-1] (one 4D site, one
+// right-hand side, one spin-colour component), in the chirality-local order:
+// chirality + (spins 0, 1) uses s as is, chirality - (spins 2, 3) uses the
+// mirrored index NS-1-s, in which L_- takes the same lower-shift form as L_+.
+// ---------------------------------------------------------------------------
+
+// coefficient table coef[chi][id][s] in global memory; the column passes
+// make chi wave-uniform so the coefficients come in through scalar loads
+template <class R, int NS>
+__device__ __forceinline__ void m5_run(const M5Prog& prog, cpx<R> (&y)[NS], const R* __restrict__ cf,
+                                       R kappa) {
+  for (int k = 0; k < prog.n; k++) {
+    const M5Op op = prog.op[k];
+    const R* d = cf + op.d * NS;
+    const R* e = cf + op.e * NS;
+    switch (op.type) {
+      case M5_SCALE: {
+#pragma unroll
+        for (int s = 0; s < NS; s++) y[s] = cscale(d[s], y[s]);
+      } break;
+      case M5_MUL_LO: {  // z_s = d_s y_s + e_s y_{s-1};  z_0 = d_0 y_0 + kappa e_0 y_{NS-1}
+        cpx<R> last = y[NS - 1];
+#pragma unroll
+        for (int s = NS - 1; s >= 1; s--) y[s] = cadd(cscale(d[s], y[s]), cscale(e[s], y[s - 1]));
+        y[0] = cadd(cscale(d[0], y[0]), cscale(kappa * e[0], last));
+      } break;
+      case M5_MUL_UP: {  // z_s = d_s y_s + e_s y_{s+1};  z_{NS-1} = d y + kappa e_{NS-1} y_0
+        cpx<R> first = y[0];
+#pragma unroll
+        for (int s = 0; s < NS - 1; s++) y[s] = cadd(cscale(d[s], y[s]), cscale(e[s], y[s + 1]));
+        y[NS - 1] = cadd(cscale(d[NS - 1], y[NS - 1]), cscale(kappa * e[NS - 1], first));
+      } break;
+      case M5_SOLVE_LO: {  // inverse of MUL_LO; d holds 1/d
+        // y_s = p_s + q_s y_{N-1}; p by forward substitution, q recomputed
+        R q = -kappa * e[0] * d[0];
+        y[0] = cscale(d[0], y[0]);
+#pragma unroll
+        for (int s = 1; s < NS; s++) {
+          q = -e[s] * q * d[s];
+          y[s] = cscale(d[s], csub(y[s], cscale(e[s], y[s - 1])));
+        }
+        const cpx<R> vl = cscale(R(1) / (R(1) - q), y[NS - 1]);
+        y[NS - 1] = vl;
+        q = -kappa * e[0] * d[0];
+#pragma unroll
+        for (int s = 0; s < NS - 1; s++) {
+          if (s > 0) q = -e[s] * q * d[s];
+          y[s] = cadd(y[s], cscale(q, vl));
+        }
+      } break;
+      case M5_SOLVE_UP: {  // inverse of MUL_UP; d holds 1/d
+        R q = -kappa * e[NS - 1] * d[NS - 1];
+        y[NS - 1] = cscale(d[NS - 1], y[NS - 1]);
+#pragma unroll
+        for (int s = NS - 2; s >= 0; s--) {
+          q = -e[s] * q * d[s];
+          y[s] = cscale(d[s], csub(y[s], cscale(e[s], y[s + 1])));
+        }
+        const cpx<R> v0 = cscale(R(1) / (R(1) - q), y[0]);
+        y[0] = v0;
+        q = -kappa * e[NS - 1] * d[NS - 1];
+#pragma unroll
+        for (int s = NS - 1; s >= 1; s--) {
+          if (s < NS - 1) q = -e[s] * q * d[s];
+          y[s] = cadd(y[s], cscale(q, v0));
+        }
+      } break;
+      default: break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column pass: buf holds [site][rhs][12 components][NS + 1] values; every
+// column (site, rhs, component) of NS values is transformed by prog.  Items
+// are ordered (chirality, site, rhs, component-of-chirality) with each
+// chirality padded to a multiple of 64, so chirality is uniform per wave.
+// blockDim.x must be a multiple of 64.  Caller synchronises around it.
+// ---------------------------------------------------------------------------
+template <class R, int NS>
+__device__ __forceinline__ void column_pass_lds(cpx<R>* buf, int nsb, int nrhs, const M5Prog& prog,
+                                                const R* coef, const R* kap) {
+  constexpr int NSP = NS + 1;
+  const int per = nsb * nrhs * 6;
+  const int ipc = (per + 63) & ~63;
+  const int lane = threadIdx.x & 63;
+  for (int base = threadIdx.x & ~63; base < 2 * ipc; base += blockDim.x) {
+    const int chi = __builtin_amdgcn_readfirstlane(base / ipc);
+    const int q = base - chi * ipc + lane;
+    if (q < per) {
+      const int c6 = q % 6;
+      const int sr = q / 6;  // sl * nrhs + r
+      const int rr = sr % nrhs;
+      cpx<R>* col = buf + ((size_t)sr * 12 + chi * 6 + c6) * NSP;
+      cpx<R> yv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; s++) yv[s] = col[chi ? NS - 1 - s : s];
+      m5_run<R, NS>(prog, yv, coef + chi * NCOEF * NS, kap[rr]);
+#pragma unroll
+      for (int s = 0; s < NS; s++) col[chi ? NS - 1 - s : s] = yv[s];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic per-right-hand-side block reduction
+// vals[k] (k < count) in LDS, key(k) gives the right-hand side of entry k.
+// Writes partial[blockIdx.x * nrhs + r].  All threads must call.
+// ---------------------------------------------------------------------------
+template <class KeyF>
+__device__ void block_reduce_rhs(double* vals, int count, int nrhs, KeyF key, double* tmp,
+                                 double* partial) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < nrhs * 16) {
+    const int r = tid / 16, q = tid % 16;
+    double acc = 0.0;
+    for (int k = q; k < count; k += 16)
+      if (key(k) == r) acc += vals[k];
+    tmp[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < nrhs) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; q++) acc += tmp[tid * 16 + q];
+    partial[(long)blockIdx.x * nrhs + tid] = acc;
+  }
+}
+
+}  // namespace odwf

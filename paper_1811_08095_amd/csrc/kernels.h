@@ -1,0 +1,60 @@
+// Host-side launchers of the libodwf HIP kernels.  All launches are
+// asynchronous on the given stream; they return the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "odwf_types.h"
+
+namespace odwf {
+
+struct Geom {
+  int L[4];  // Lx, Ly, Lz, Lt
+  long V, h;
+};
+
+// hopping kernel (hop.hip)
+hipError_t launch_hop(const HopArgs& a, int prec, int Ns, hipStream_t st);
+int hop_nblocks(int h, int nrhs, int Ns);
+
+// layouts (pack.hip)
+// canonical complex128 [rhs][s][t][z][y][x][4][3] (rhs offset r0, nrhs of them)
+// <-> internal half of parity `par`.
+hipError_t launch_pack_spinor(int prec, const void* canon, int r0, void* out, float* out_sc,
+                              int par, int nrhs, int Ns, const Geom& g, hipStream_t st);
+hipError_t launch_unpack_spinor(int prec, const void* in, const float* in_sc, void* canon, int r0,
+                                int par, int nrhs, int Ns, const Geom& g, hipStream_t st);
+// zero the sites of parity par of a canonical field (rhs r0 .. r0+nrhs-1)
+hipError_t launch_zero_canon_parity(void* canon, int r0, int par, int nrhs, int Ns, const Geom& g,
+                                    hipStream_t st);
+// gauge: canonical complex128 [t][z][y][x][mu][3][3] -> per-parity link
+// arrays [h][8][18 doubles] (prec64) or [h][8][12 floats] (reduced)
+hipError_t launch_pack_gauge(const void* canon, void* out, int par, int prec, const Geom& g,
+                             hipStream_t st);
+
+// fifth-dimension programs on a half field (m5.hip), FP64 or FP32 storage:
+// out = c0 * prog(in) + c1 * other   (other may be null)
+hipError_t launch_m5(int prec, const void* in, const float* in_sc, void* out, float* out_sc,
+                     const void* other, const float* other_sc, double c0, double c1,
+                     const M5Prog& prog, const void* coef, const KappaArr& kappa, long h, int nrhs,
+                     int Ns, hipStream_t st);
+
+// BLAS-1 on half fields (blas.hip); n5 = h * nrhs * Ns five-dimensional sites
+hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st);
+// dst = src (accumulate: dst += src), converting storage precision
+hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc, int prec_dst,
+                              void* dst, float* dst_sc, int accumulate, const int* rhs_mask,
+                              long h, int nrhs, int Ns, hipStream_t st);
+// y = x + beta_r y for active right-hand sides
+hipError_t launch_vec_xpby(int prec, const void* x, const float* x_sc, void* y, float* y_sc,
+                           const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st);
+// per-block partial sums of |v|^2 per right-hand side
+hipError_t launch_vec_norm2(int prec, const void* v, const float* sc, double* partial, long h,
+                            int nrhs, int Ns, int* nblocks_out, hipStream_t st);
+int vec_nblocks(long h, int nrhs, int Ns);
+
+// scalar finalisation (blas.hip), one block
+enum FinKind { FIN_SUM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3, FIN_F2 = 4, FIN_TRUE = 5 };
+hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
+                      double* out, hipStream_t st);
+
+}  // namespace odwf

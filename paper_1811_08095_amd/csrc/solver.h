@@ -1,0 +1,35 @@
+// Operator sequences and solvers built on the fused kernels.
+#pragma once
+#include "runtime.h"
+
+namespace odwf {
+
+// D = omega (A + W)(1 + L) on full fields given as (even, odd) halves;
+// te/to are scratch halves.
+hipError_t apply_D(const OpCtx& c, const HV& ie, const HV& io, const HV& te, const HV& to,
+                   const HV& oe, const HV& oo);
+// D^dag = (1 + L)^dag (A^dag + W^dag) omega
+hipError_t apply_Ddag(const OpCtx& c, const HV& ie, const HV& io, const HV& te, const HV& to,
+                      const HV& oe, const HV& oo);
+// S_e in (to: odd scratch)
+hipError_t apply_schur(const OpCtx& c, const HV& in, const HV& to, const HV& out);
+// S_e^dag in
+hipError_t apply_schur_dag(const OpCtx& c, const HV& in, const HV& te, const HV& to, const HV& out);
+
+// Fused CG pieces of the normal operator N = S_e^dag S_e applied to p:
+//   K1: t = A^{-1} W_oe p
+//   K2: v = A^{-dag} (p - A^{-1} W_eo t), partial |S_e p|^2 (if partial_u)
+//   K3: t = A^{-dag} W^dag_oe v
+//   K4: out = A^dag v - W^dag_eo t
+// With k4 options the last step can instead update r, x (CG step) or write a
+// residual f - N p.
+hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, const HV& out,
+                        double* partial_u, const HopOpt* k4 = nullptr);
+
+odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double* tol, int r0,
+                        int nrhs, int inner, int maxiter, const void* b, void* x, int use_x0,
+                        odwf_stats* stats, hipStream_t st);
+
+size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner);
+
+}  // namespace odwf

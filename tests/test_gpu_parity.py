@@ -1,0 +1,122 @@
+"""GPU parity of every operator of the C ABI against the FP64 CPU oracle.
+
+FP64: relative error |out - ref| / |ref| <= 1e-12 (rounding order only).
+Reduced precisions: error against the FP64 oracle stated per format.
+Lattices cover the 2^4 aliasing case (x + mu = x - mu), non-cubic extents,
+both time boundary conditions, ragged final blocks (h not a multiple of the
+sites per block) and several right-hand sides with different masses.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1811_08095_amd import odwf, synth
+
+pytestmark = pytest.mark.gpu
+
+M0 = 1.3
+OPS = [odwf.OP_HOP_EO, odwf.OP_HOP_OE, odwf.OP_M5INV, odwf.OP_D, odwf.OP_DDAG, odwf.OP_DDAGD,
+       odwf.OP_SCHUR, odwf.OP_SCHUR_DAG, odwf.OP_SCHUR_NORMAL]
+OP_NAMES = ["HOP_EO", "HOP_OE", "M5INV", "D", "DDAG", "DDAGD", "SCHUR", "SCHUR_DAG", "SCHUR_NORMAL"]
+
+# (dims X,Y,Z,T, Ns, bc_t, eps, seed)
+CASES = [
+    ((2, 2, 2, 2), 4, -1, 0.5, 3),
+    ((4, 4, 4, 4), 8, -1, 0.3, 0),     # 4^4 x 8, the plain FP64 configuration
+    ((4, 2, 6, 4), 4, 1, 0.7, 5),      # non-cubic, periodic in t
+    ((6, 2, 2, 2), 16, -1, 0.5, 7),    # Ns = 16, ragged final block (h = 24)
+    ((2, 4, 2, 6), 32, -1, 0.5, 9),    # Ns = 32
+]
+MASSES = [0.05, 0.5, 2.6]
+
+_cache = {}
+
+
+def _setup(case):
+    if case in _cache:
+        return _cache[case]
+    import torch
+    dims, Ns, bc, eps, seed = case
+    U = synth.make_gauge(dims, eps, seed)
+    w = odwf.zolotarev_omega(Ns, 0.05, 6.2)
+    lat = odwf.Lattice(dims, bc_t=bc)
+    lat.load_gauge(U)
+    sol = odwf.Solver(lat, Ns, M0, w)
+    psi = synth.make_source(dims, Ns, len(MASSES), 1000 + seed)
+    _cache[case] = (U, w, lat, sol, psi, torch.from_numpy(psi).cuda())
+    return _cache[case]
+
+
+def _ref(op, U, psi, w, mq, bc):
+    return oracle.apply(op, U, psi, M0, w, mq / (2 * M0), bc)
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])) + f"_Ns{c[1]}_bc{c[2]}")
+@pytest.mark.parametrize("opi", range(len(OPS)), ids=OP_NAMES)
+def test_fp64_operator_parity(case, opi):
+    U, w, lat, sol, psi, psid = _setup(case)
+    op = OPS[opi]
+    print(f"case {case} op {OP_NAMES[opi]}", flush=True)
+    out = sol.apply(op, psid, MASSES, prec=odwf.FP64).cpu().numpy()
+    for r, mq in enumerate(MASSES):
+        ref = _ref(op, U, psi[r], w, mq, case[2])
+        err = _relerr(out[r], ref)
+        assert err <= 1e-12, (OP_NAMES[opi], mq, err)
+
+
+# stated bounds of the reduced-precision operators against FP64
+PREC_BOUND = {odwf.FP32: 1e-5, odwf.FP16S: 4e-3, odwf.BF16S: 3e-2}
+
+
+@pytest.mark.parametrize("prec", [odwf.FP32, odwf.FP16S, odwf.BF16S], ids=["fp32", "fp16s", "bf16s"])
+@pytest.mark.parametrize("opi", [0, 3, 6, 8], ids=["HOP_EO", "D", "SCHUR", "SCHUR_NORMAL"])
+def test_reduced_precision_operator_error(prec, opi):
+    case = CASES[3]
+    U, w, lat, sol, psi, psid = _setup(case)
+    out = sol.apply(OPS[opi], psid, MASSES, prec=prec).cpu().numpy()
+    errs = []
+    for r, mq in enumerate(MASSES):
+        ref = _ref(OPS[opi], U, psi[r], w, mq, case[2])
+        errs.append(_relerr(out[r], ref))
+    print(f"{odwf.PREC_NAMES[prec]} {OP_NAMES[opi]} rel err vs FP64: {max(errs):.3e}")
+    assert max(errs) <= PREC_BOUND[prec]
+    assert max(errs) > 0  # it really ran in reduced precision
+
+
+def test_fp64_parity_16x4_Ns16():
+    """16^4 x 16 (the mixed-precision solve configuration's lattice): the hop
+    and the normal operator at the size where many blocks run."""
+    import torch
+    dims, Ns = (16, 16, 16, 16), 16
+    U = synth.make_gauge(dims, 0.5, 0)
+    w = odwf.zolotarev_omega(Ns, 0.05, 6.2)
+    lat = odwf.Lattice(dims, bc_t=-1)
+    lat.load_gauge(U)
+    sol = odwf.Solver(lat, Ns, M0, w)
+    psi = synth.make_source(dims, Ns, 1, 1001)
+    psid = torch.from_numpy(psi).cuda()
+    for op in (odwf.OP_HOP_EO, odwf.OP_SCHUR_NORMAL):
+        out = sol.apply(op, psid, [0.04]).cpu().numpy()[0]
+        ref = _ref(op, U, psi[0], w, 0.04, -1)
+        assert _relerr(out, ref) <= 1e-12
+
+
+def test_apply_is_deterministic():
+    U, w, lat, sol, psi, psid = _setup(CASES[1])
+    a = sol.apply(odwf.OP_SCHUR_NORMAL, psid, MASSES).cpu().numpy()
+    b = sol.apply(odwf.OP_SCHUR_NORMAL, psid, MASSES).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_rhs_independence():
+    """Each right-hand side of a multi-RHS launch equals its single-RHS result
+    bit for bit (the per-RHS mass and arithmetic do not depend on the batch)."""
+    U, w, lat, sol, psi, psid = _setup(CASES[1])
+    multi = sol.apply(odwf.OP_SCHUR_NORMAL, psid, MASSES).cpu().numpy()
+    for r, mq in enumerate(MASSES):
+        single = sol.apply(odwf.OP_SCHUR_NORMAL, psid[r:r + 1].contiguous(), [mq]).cpu().numpy()[0]
+        np.testing.assert_allclose(single, multi[r], rtol=0, atol=1e-14 * np.abs(multi[r]).max())
