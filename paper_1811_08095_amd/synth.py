@@ -70,3 +70,41 @@ def unit_gauge(dims) -> np.ndarray:
     U = np.zeros((T, Z, Y, X, 4, 3, 3), np.complex128)
     U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1.0
     return U
+
+
+# ---------------------------------------------------------------------------
+# device-side generators for lattices too large to draw on the host in
+# reasonable time (64^4 x 16 sources hold 3.2e9 complex numbers).  Same
+# distributions; the stream is torch's seeded device generator (Philox), drawn
+# in t-slices in the canonical order.
+# ---------------------------------------------------------------------------
+
+def make_gauge_device(dims, eps: float, seed: int, device="cuda"):
+    """U = exp(i eps H) as a complex128 CUDA tensor [t][z][y][x][4][3][3]."""
+    import torch
+    X, Y, Z, T = (int(d) for d in dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    lam = torch.from_numpy((gell_mann() * 0.5).reshape(8, 9)).to(device)
+    out = torch.empty((T, Z, Y, X, 4, 3, 3), dtype=torch.complex128, device=device)
+    for t in range(T):
+        h = torch.randn((Z * Y * X * 4, 8), generator=g, device=device, dtype=torch.float64)
+        H = (h.to(torch.complex128) @ lam).reshape(-1, 3, 3)
+        H = 0.5 * (H + H.transpose(-1, -2).conj())
+        out[t] = torch.linalg.matrix_exp(1j * eps * H).reshape(Z, Y, X, 4, 3, 3)
+    return out
+
+
+def make_source_device(dims, Ns: int, nrhs: int, seed: int, device="cuda"):
+    """Complex Gaussian source (Re, Im ~ N(0,1)) as a CUDA tensor
+    [rhs][s][t][z][y][x][4][3]."""
+    import torch
+    X, Y, Z, T = (int(d) for d in dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty((nrhs, Ns, T, Z, Y, X, 4, 3), dtype=torch.complex128, device=device)
+    v = torch.view_as_real(out)
+    for r in range(nrhs):
+        for s in range(Ns):
+            v[r, s].normal_(generator=g)
+    return out
