@@ -23,11 +23,13 @@ int vec_nblocks(long h, int nrhs, int Ns) {
 }
 
 template <class P>
-__global__ void vec_zero_kernel(void* v, float* sc, long h, int nrhs, int Ns) {
+__global__ void vec_zero_kernel(void* v, float* sc, const CGScal* gate, int gate_mode, long h, int nrhs,
+                                int Ns) {
   using R = typename P::real;
   const int inner = nrhs * Ns;
   const int spb = blockDim.x / inner;
   const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
+  if (!gate_on(gate, gate_mode, r)) return;
   cpx<R> z[12];
 #pragma unroll
   for (int c = 0; c < 12; c++) z[c] = {R(0), R(0)};
@@ -37,13 +39,14 @@ __global__ void vec_zero_kernel(void* v, float* sc, long h, int nrhs, int Ns) {
 
 template <class PS, class PD>
 __global__ void vec_convert_kernel(const void* src, const float* src_sc, void* dst, float* dst_sc,
-                                   int accumulate, const int* rhs_mask, long h, int nrhs, int Ns) {
+                                   int accumulate, const CGScal* gate, int gate_mode, long h, int nrhs,
+                                   int Ns) {
   using RS = typename PS::real;
   using RD = typename PD::real;
   const int inner = nrhs * Ns;
   const int spb = blockDim.x / inner;
   const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
-  if (rhs_mask && !rhs_mask[r]) return;
+  if (!gate_on(gate, gate_mode, r)) return;
   for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb) {
     cpx<RS> a[12];
     load_site<PS>(src, src_sc, j, r, s, nrhs, Ns, a);
@@ -109,37 +112,38 @@ __global__ void vec_norm2_kernel(const void* v, const float* sc, double* partial
     default: return hipErrorInvalidValue;                                               \
   }
 
-hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st) {
+hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st,
+                           const CGScal* gate, int gate_mode) {
   const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
   const dim3 gr(vec_nblocks(h, nrhs, Ns));
-  ODWF_PREC_SWITCH(prec, vec_zero_kernel, gr, dim3(block), 0, st, v, sc, h, nrhs, Ns);
+  ODWF_PREC_SWITCH(prec, vec_zero_kernel, gr, dim3(block), 0, st, v, sc, gate, gate_mode, h, nrhs, Ns);
   return hipGetLastError();
 }
 
 template <class PS>
 static hipError_t convert_to(int prec_dst, const void* src, const float* src_sc, void* dst,
-                             float* dst_sc, int acc, const int* mask, long h, int nrhs, int Ns,
-                             hipStream_t st) {
+                             float* dst_sc, int acc, const CGScal* gate, int gm, long h, int nrhs,
+                             int Ns, hipStream_t st) {
   const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
   const dim3 gr(vec_nblocks(h, nrhs, Ns));
   switch (prec_dst) {
-    case PREC64: hipLaunchKernelGGL((vec_convert_kernel<PS, SP64>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
-    case PREC32: hipLaunchKernelGGL((vec_convert_kernel<PS, SP32>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
-    case PREC16: hipLaunchKernelGGL((vec_convert_kernel<PS, SP16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
-    case PRECB16: hipLaunchKernelGGL((vec_convert_kernel<PS, SPB16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, mask, h, nrhs, Ns); break;
+    case PREC64: hipLaunchKernelGGL((vec_convert_kernel<PS, SP64>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, gate, gm, h, nrhs, Ns); break;
+    case PREC32: hipLaunchKernelGGL((vec_convert_kernel<PS, SP32>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, gate, gm, h, nrhs, Ns); break;
+    case PREC16: hipLaunchKernelGGL((vec_convert_kernel<PS, SP16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, gate, gm, h, nrhs, Ns); break;
+    case PRECB16: hipLaunchKernelGGL((vec_convert_kernel<PS, SPB16>), gr, dim3(block), 0, st, src, src_sc, dst, dst_sc, acc, gate, gm, h, nrhs, Ns); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc, int prec_dst,
-                              void* dst, float* dst_sc, int accumulate, const int* rhs_mask, long h,
-                              int nrhs, int Ns, hipStream_t st) {
+                              void* dst, float* dst_sc, int accumulate, long h, int nrhs, int Ns,
+                              hipStream_t st, const CGScal* gate, int gate_mode) {
   switch (prec_src) {
-    case PREC64: return convert_to<SP64>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
-    case PREC32: return convert_to<SP32>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
-    case PREC16: return convert_to<SP16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
-    case PRECB16: return convert_to<SPB16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, rhs_mask, h, nrhs, Ns, st);
+    case PREC64: return convert_to<SP64>(prec_dst, src, src_sc, dst, dst_sc, accumulate, gate, gate_mode, h, nrhs, Ns, st);
+    case PREC32: return convert_to<SP32>(prec_dst, src, src_sc, dst, dst_sc, accumulate, gate, gate_mode, h, nrhs, Ns, st);
+    case PREC16: return convert_to<SP16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, gate, gate_mode, h, nrhs, Ns, st);
+    case PRECB16: return convert_to<SPB16>(prec_dst, src, src_sc, dst, dst_sc, accumulate, gate, gate_mode, h, nrhs, Ns, st);
   }
   return hipErrorInvalidValue;
 }
@@ -161,11 +165,65 @@ hipError_t launch_vec_norm2(int prec, const void* v, const float* sc, double* pa
   return hipGetLastError();
 }
 
+// copy right-hand side r_src of an nrhs_src field into right-hand side r_dst
+// of an nrhs_dst field (same parity, any storage precisions); src == nullptr
+// writes zeros
+template <class PS, class PD>
+__global__ void vec_copy_rhs_kernel(const void* src, const float* src_sc, int nrhs_src, int r_src,
+                                    void* dst, float* dst_sc, int nrhs_dst, int r_dst, long h, int Ns) {
+  using RS = typename PS::real;
+  using RD = typename PD::real;
+  const long n = h * Ns;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const long j = k / Ns;
+    const int s = (int)(k % Ns);
+    cpx<RD> b[12];
+    if (src) {
+      cpx<RS> a[12];
+      load_site<PS>(src, src_sc, j, r_src, s, nrhs_src, Ns, a);
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c] = {(RD)a[c].re, (RD)a[c].im};
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c] = {RD(0), RD(0)};
+    }
+    store_site<PD>(dst, dst_sc, j, r_dst, s, nrhs_dst, Ns, b);
+  }
+}
+
+template <class PS>
+static hipError_t copy_rhs_to(int prec_dst, const void* src, const float* src_sc, int ns, int rs,
+                              void* dst, float* dst_sc, int nd, int rd, long h, int Ns, hipStream_t st) {
+  long nb = (h * Ns + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  const dim3 gr((unsigned)nb);
+  switch (prec_dst) {
+    case PREC64: hipLaunchKernelGGL((vec_copy_rhs_kernel<PS, SP64>), gr, dim3(256), 0, st, src, src_sc, ns, rs, dst, dst_sc, nd, rd, h, Ns); break;
+    case PREC32: hipLaunchKernelGGL((vec_copy_rhs_kernel<PS, SP32>), gr, dim3(256), 0, st, src, src_sc, ns, rs, dst, dst_sc, nd, rd, h, Ns); break;
+    case PREC16: hipLaunchKernelGGL((vec_copy_rhs_kernel<PS, SP16>), gr, dim3(256), 0, st, src, src_sc, ns, rs, dst, dst_sc, nd, rd, h, Ns); break;
+    case PRECB16: hipLaunchKernelGGL((vec_copy_rhs_kernel<PS, SPB16>), gr, dim3(256), 0, st, src, src_sc, ns, rs, dst, dst_sc, nd, rd, h, Ns); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_copy_rhs(int prec_src, const void* src, const float* src_sc, int nrhs_src,
+                               int r_src, int prec_dst, void* dst, float* dst_sc, int nrhs_dst,
+                               int r_dst, long h, int Ns, hipStream_t st) {
+  switch (prec_src) {
+    case PREC64: return copy_rhs_to<SP64>(prec_dst, src, src_sc, nrhs_src, r_src, dst, dst_sc, nrhs_dst, r_dst, h, Ns, st);
+    case PREC32: return copy_rhs_to<SP32>(prec_dst, src, src_sc, nrhs_src, r_src, dst, dst_sc, nrhs_dst, r_dst, h, Ns, st);
+    case PREC16: return copy_rhs_to<SP16>(prec_dst, src, src_sc, nrhs_src, r_src, dst, dst_sc, nrhs_dst, r_dst, h, Ns, st);
+    case PRECB16: return copy_rhs_to<SPB16>(prec_dst, src, src_sc, nrhs_src, r_src, dst, dst_sc, nrhs_dst, r_dst, h, Ns, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------------------
 // finalisation: one block of 256 threads
 // ---------------------------------------------------------------------------
 __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
-                           double* out) {
+                           double* out, int gated) {
   __shared__ double red[256];
   __shared__ double sums[MAXRHS];
   for (int r = 0; r < nrhs; r++) {
@@ -186,6 +244,7 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
   if (out) out[r] = v;
   if (!scal) return;
   CGScal c = scal[r];
+  if (gated && !c.update) return;  // only the right-hand sides that asked for it
   const bool finite = isfinite(v);
   switch (kind) {
     case FIN_F2:
@@ -216,10 +275,16 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
           c.beta = v / c.rr;
           c.rr = v;
           if (v > c.rmax2) c.rmax2 = v;
-          if (v <= c.tol2 * c.f2) {
+          const bool met = v <= c.tol2 * c.f2;
+          const bool capped = c.iters >= c.maxiter;
+          if (c.confirm) {
+            // the decision is left to the true residual of the update that follows
+            if (met || capped) c.update = 1;
+            if (capped) c.active = 0;
+          } else if (met) {
             c.converged = 1;
             c.active = 0;
-          } else if (c.iters >= c.maxiter) {
+          } else if (capped) {
             c.active = 0;
           }
           if (c.delta2 > 0.0 && v < c.delta2 * c.rmax2) c.update = 1;
@@ -233,6 +298,7 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
       c.rr = v;
       c.rmax2 = v;
       c.update = 0;
+      c.nupd += 1;
       if (!finite) {
         c.nan = 1;
         c.active = 0;
@@ -251,8 +317,9 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
 }
 
 hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
-                      double* out, hipStream_t st) {
-  hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, st, kind, partial, nblocks, nrhs, scal, out);
+                      double* out, hipStream_t st, int gated) {
+  hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, st, kind, partial, nblocks, nrhs, scal, out,
+                     gated);
   return hipGetLastError();
 }
 

@@ -6,9 +6,10 @@
 // Internal spinor layout of one parity half (h = V/2 sites), per site j,
 // right-hand side r, fifth-dimension slice s and spin-colour component
 // c = spin*3 + colour (12 complex per 5D site):
-//     chunk (j, cg, r, s) of CPB consecutive complex numbers, cg = c / CPB,
-//     address = ((j * NCG + cg) * nrhs + r) * Ns + s   (in 16-byte chunks),
-// so the Ns * nrhs lanes of one site read consecutive 16-byte chunks.  The
+//     chunk (j, r, cg, s) of CPB consecutive complex numbers, cg = c / CPB,
+//     address = ((j * nrhs + r) * NCG + cg) * Ns + s   (in 16-byte chunks),
+// so the Ns lanes of one (site, rhs) read consecutive 16-byte chunks and the
+// chunk stride within a 5D site is the compile-time Ns.  The
 // reduced-precision formats keep one float scale per 5D site (j, r, s) at
 // (j * nrhs + r) * Ns + s; stored values are component / scale with scale the
 // largest |real| or |imag| part of the 24 reals.
@@ -170,11 +171,10 @@ __device__ __forceinline__ void load_site(const void* base, const float* scale, 
                                           int nrhs, int Ns, cpx<typename P::real> (&v)[12]) {
   constexpr int NCG = 12 / P::CPB;
   const uint4* b = reinterpret_cast<const uint4*>(base);
-  const long inner = (long)nrhs * Ns;
-  const long off = j * NCG * inner + (long)r * Ns + s;
+  const long off = ((j * nrhs + r) * NCG) * Ns + s;
   uint4 q[NCG];
 #pragma unroll
-  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * inner];
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
 #pragma unroll
   for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
   if constexpr (P::SCALED) {
@@ -191,11 +191,10 @@ __device__ __forceinline__ void load_site_cached(const void* base, const float* 
                                                  cpx<typename P::real> (&v)[12]) {
   constexpr int NCG = 12 / P::CPB;
   const uint4* b = reinterpret_cast<const uint4*>(base);
-  const long inner = (long)nrhs * Ns;
-  const long off = j * NCG * inner + (long)r * Ns + s;
+  const long off = ((j * nrhs + r) * NCG) * Ns + s;
   uint4 q[NCG];
 #pragma unroll
-  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * inner];
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
 #pragma unroll
   for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
   if constexpr (P::SCALED) {
@@ -211,8 +210,7 @@ __device__ __forceinline__ void store_site(void* base, float* scale, long j, int
   using R = typename P::real;
   constexpr int NCG = 12 / P::CPB;
   uint4* b = reinterpret_cast<uint4*>(base);
-  const long inner = (long)nrhs * Ns;
-  const long off = j * NCG * inner + (long)r * Ns + s;
+  const long off = ((j * nrhs + r) * NCG) * Ns + s;
   R inv = R(1);
   if constexpr (P::SCALED) {
     float m = 0.f;
@@ -222,7 +220,20 @@ __device__ __forceinline__ void store_site(void* base, float* scale, long j, int
     inv = m > 0.f ? 1.0f / m : 0.f;
   }
 #pragma unroll
-  for (int cg = 0; cg < NCG; cg++) b[off + cg * inner] = pack_chunk<P>(&v[cg * P::CPB], inv);
+  for (int cg = 0; cg < NCG; cg++) b[off + cg * Ns] = pack_chunk<P>(&v[cg * P::CPB], inv);
+}
+
+// is right-hand side r selected by the gate?
+__device__ __forceinline__ bool gate_on(const CGScal* g, int mode, int r) {
+  if (!g || mode == GATE_NONE) return true;
+  return mode == GATE_ACTIVE ? g[r].active != 0 : g[r].update != 0;
+}
+// does any right-hand side of the launch pass the gate? (block-uniform)
+__device__ __forceinline__ bool gate_any(const CGScal* g, int mode, int nrhs) {
+  if (!g || mode == GATE_NONE) return true;
+  bool any = false;
+  for (int r = 0; r < nrhs; r++) any |= gate_on(g, mode, r);
+  return any;
 }
 
 // ---------------------------------------------------------------------------

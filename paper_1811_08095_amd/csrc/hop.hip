@@ -186,8 +186,58 @@ __device__ __forceinline__ void hop_one(const cpx<R> (&psi)[12], const cpx<R>* U
   reconstruct<MU, SIG>(g, acc);
 }
 
-template <class P, int NS, bool DAG>
-__global__ void __launch_bounds__(256, 2) hop_kernel(const HopArgs a) {
+// first site of this block under the configured traversal
+__device__ __forceinline__ long block_first_site(const HopArgs& a) {
+  int lb = blockIdx.x;
+  if (a.xcd) {
+    // hardware dispatches block b to XCD b % 8; give XCD x the contiguous
+    // logical range [start(x), start(x) + count(x))
+    const int q = a.nblocks >> 3, rem = a.nblocks & 7;
+    const int x = lb & 7, k = lb >> 3;
+    lb = x * q + min(x, rem) + k;
+  }
+  if (a.tile_y > 0) {
+    const int hx = a.L[0] >> 1;
+    const int nseg = hx / a.spb;
+    int rest = lb;
+    const int seg = rest % nseg;
+    rest /= nseg;
+    const int yi = rest % a.tile_y;
+    rest /= a.tile_y;
+    const int zi = rest % a.tile_z;
+    rest /= a.tile_z;
+    const int t = rest % a.L[3];
+    rest /= a.L[3];
+    const int nty = a.L[1] / a.tile_y;
+    const int y = (rest % nty) * a.tile_y + yi;
+    const int z = (rest / nty) * a.tile_z + zi;
+    return (((long)t * a.L[2] + z) * a.L[1] + y) * hx + (long)seg * a.spb;
+  }
+  return (long)lb * a.spb;
+}
+
+#ifndef ODWF_HOP_GROUP64
+#define ODWF_HOP_GROUP64 1
+#endif
+#ifndef ODWF_HOP_GROUP32
+#define ODWF_HOP_GROUP32 2
+#endif
+
+// neighbour loads issued together before any of them is used: enough bytes
+// in flight per wave to cover HBM latency at the occupancy the kernel reaches
+template <class P>
+struct HopGroup {
+  static constexpr int G = sizeof(typename P::real) == 8 ? ODWF_HOP_GROUP64 : ODWF_HOP_GROUP32;
+};
+
+// minimum waves per SIMD the register allocation must allow
+template <class P, bool PLAIN>
+struct HopWaves {
+  static constexpr int W = sizeof(typename P::real) == 8 ? (PLAIN ? 2 : 1) : (PLAIN ? 4 : 2);
+};
+
+template <class P, int NS, bool DAG, bool PLAIN>
+__global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const HopArgs a) {
   using R = typename P::real;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nrhs = a.nrhs;
@@ -197,28 +247,44 @@ __global__ void __launch_bounds__(256, 2) hop_kernel(const HopArgs a) {
   const int lr = tid - sl * inner;
   const int r = lr / NS;
   const int s = lr - r * NS;
-  const long j0 = (long)blockIdx.x * a.spb;
+  if (!gate_any(a.gate, a.gate_mode, nrhs)) return;  // whole block idle
+  const long j0 = block_first_site(a);
   const int nsb = (int)min((long)a.spb, (long)a.h - j0);
-  const bool valid = sl < nsb;  // padded threads have sl >= spb >= nsb
+  // padded threads have sl >= spb >= nsb; gated-off right-hand sides do no work
+  const bool valid = sl < nsb && gate_on(a.gate, a.gate_mode, r);
   const long j = j0 + sl;
   constexpr int NSP = NS + 1;
 
   // LDS carve-up: links, then (aliased) the column buffer; reduction scratch
+  // links and the column buffer live in separate regions, so an x term can be
+  // transformed in LDS while the links are staged and used
   const size_t lnk_n = (size_t)a.spb * 8 * 9;
-  const size_t buf_n = (size_t)a.spb * nrhs * 12 * NSP;
+  const size_t buf_n = PLAIN ? 0 : (size_t)a.spb * nrhs * 12 * NSP;
   cpx<R>* lnk = reinterpret_cast<cpx<R>*>(smem);
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem);
-  const size_t region = (lnk_n > buf_n ? lnk_n : buf_n) * sizeof(cpx<R>);
+  cpx<R>* buf = lnk + lnk_n;
+  const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   R* kap = reinterpret_cast<R*>(smem + region);
   double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
   double* rtmp = red + blockDim.x;
   const R* coef = reinterpret_cast<const R*>(a.coef);
-  if (tid < nrhs) kap[tid] = (R)a.kappa[tid];
+  if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
   stage_links<P>(a.links, j0, nsb, lnk);
 
-  // x term (same parity), loaded early
   cpx<R> xv[12];
-  const bool has_x = a.xin != nullptr;
+  const bool has_x = !PLAIN && a.xin != nullptr;
+  // x term with its own fifth-dimension program: transform it in LDS before the
+  // hop, so no column pass runs while the hop accumulators are live
+  const bool x_first = has_x && a.prog_x.n > 0;
+  if (x_first) {
+    if (valid) {
+      load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+      cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c * NSP] = xv[c];
+    }
+    __syncthreads();
+    column_pass_lds<R, NS>(buf, nsb, nrhs, a.prog_x, coef, kap);
+  }
   __syncthreads();
 
   cpx<R> acc[12];
@@ -228,56 +294,73 @@ __global__ void __launch_bounds__(256, 2) hop_kernel(const HopArgs a) {
   if (valid) {
     const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
     const int hx = L0 >> 1;
-    const int xh = (int)(j % hx);
-    long rest = j / hx;
-    const int y = (int)(rest % L1);
-    rest /= L1;
-    const int z = (int)(rest % L2);
-    const int t = (int)(rest / L2);
-    const int x = 2 * xh + ((y + z + t + a.out_par) & 1);
+    // site coordinates: when a block lies inside one x-row (always for the
+    // tiled traversal) y, z, t are block-uniform and only x varies by lane
+    int x, y, z, t;
+    if (hx % a.spb == 0) {
+      const int xh0 = (int)(j0 % hx);
+      long rest = j0 / hx;
+      y = (int)(rest % L1);
+      rest /= L1;
+      z = (int)(rest % L2);
+      t = (int)(rest / L2);
+      x = 2 * (xh0 + sl) + ((y + z + t + a.out_par) & 1);
+    } else {
+      const int xh = (int)(j % hx);
+      long rest = j / hx;
+      y = (int)(rest % L1);
+      rest /= L1;
+      z = (int)(rest % L2);
+      t = (int)(rest / L2);
+      x = 2 * xh + ((y + z + t + a.out_par) & 1);
+    }
     const cpx<R>* U = lnk + (size_t)sl * 8 * 9;
-    const R bcs = (R)a.bc_t;
-    // one neighbour at a time keeps the register footprint of a lane small;
-    // the block's many resident waves provide the memory-level parallelism
+    const bool flip_f = a.bc_t < 0 && t + 1 == L3;  // forward t hop wraps
+    const bool flip_b = a.bc_t < 0 && t == 0;       // backward t hop wraps
+    constexpr int G = HopGroup<P>::G;
+    // direction order: +x, -x, +y, -y, ... (4-7 are the backward hops)
 #pragma unroll 1
-    for (int dir = 0; dir < 8; dir++) {
-      const int mu = dir & 3;
-      const bool fwd = dir < 4;
-      int xx = x, yy = y, zz = z, tt = t;
-      R sgn = R(1);
-      switch (mu) {
-        case 0: xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1); break;
-        case 1: yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1); break;
-        case 2: zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1); break;
-        default:
-          if (fwd) {
-            tt = t + 1 == L3 ? 0 : t + 1;
-            if (t + 1 == L3) sgn = bcs;
-          } else {
-            tt = t == 0 ? L3 - 1 : t - 1;
-            if (t == 0) sgn = bcs;
-          }
-          break;
-      }
-      const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
-      cpx<R> psi[12];
-      load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi);
-      if (sgn < R(0)) {
+    for (int g0 = 0; g0 < 8; g0 += G) {
+      cpx<R> psi[G][12];
 #pragma unroll
-        for (int k = 0; k < 12; k++) psi[k] = {-psi[k].re, -psi[k].im};
+      for (int k = 0; k < G; k++) {
+        const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);  // 0,4,1,5,2,6,3,7
+        const int mu = dir & 3;
+        const bool fwd = dir < 4;
+        int xx = x, yy = y, zz = z, tt = t;
+        if (mu == 0) xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1);
+        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
+        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
+        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
+        const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
+        load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
       }
-      // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
-      const bool minus = fwd != DAG;
-      switch (dir) {
-        case 0: case 4: if (minus) hop_one<0, +1>(psi, U + dir * 9, acc); else hop_one<0, -1>(psi, U + dir * 9, acc); break;
-        case 1: case 5: if (minus) hop_one<1, +1>(psi, U + dir * 9, acc); else hop_one<1, -1>(psi, U + dir * 9, acc); break;
-        case 2: case 6: if (minus) hop_one<2, +1>(psi, U + dir * 9, acc); else hop_one<2, -1>(psi, U + dir * 9, acc); break;
-        default: if (minus) hop_one<3, +1>(psi, U + dir * 9, acc); else hop_one<3, -1>(psi, U + dir * 9, acc); break;
+#pragma unroll
+      for (int k = 0; k < G; k++) {
+        const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);
+        const bool fwd = dir < 4;
+        if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
+#pragma unroll
+          for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
+        }
+        // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
+        const bool minus = fwd != DAG;
+        switch (dir & 3) {
+          case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
+          case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
+          case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
+          default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
+        }
       }
     }
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
   }
+  if constexpr (PLAIN) {
+    if (valid) store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+    return;
+  }
+
   // ---- fifth-dimension column passes --------------------------------------
   auto column_pass = [&](const M5Prog& prog, cpx<R>(&v)[12]) {
     __syncthreads();
@@ -296,10 +379,17 @@ __global__ void __launch_bounds__(256, 2) hop_kernel(const HopArgs a) {
     }
   };
 
-  if (a.prog_h.n > 0) column_pass(a.prog_h, acc);
-  if (has_x && valid) load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+  if (a.prog_h.n > 0) column_pass(a.prog_h, acc);  // never together with x_first
+  if (has_x && valid) {
+    if (x_first) {
+      const cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
+#pragma unroll
+      for (int c = 0; c < 12; c++) xv[c] = b[c * NSP];
+    } else {
+      load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+    }
+  }
   if (has_x) {
-    if (a.prog_x.n > 0) column_pass(a.prog_x, xv);
     const R ch = (R)a.c_h, cx = (R)a.c_x;
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = cadd(cscale(ch, acc[c]), cscale(cx, xv[c]));
@@ -360,11 +450,11 @@ __global__ void __launch_bounds__(256, 2) hop_kernel(const HopArgs a) {
 }
 
 template <class P, int NS>
-static size_t hop_smem(int spb, int nrhs, int block) {
+static size_t hop_smem(int spb, int nrhs, int block, bool plain) {
   using R = typename P::real;
   const size_t lnk_n = (size_t)spb * 8 * 9;
-  const size_t buf_n = (size_t)spb * nrhs * 12 * (NS + 1);
-  const size_t region = (lnk_n > buf_n ? lnk_n : buf_n) * sizeof(cpx<R>);
+  const size_t buf_n = plain ? 0 : (size_t)spb * nrhs * 12 * (NS + 1);
+  const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   size_t off = (region + MAXRHS * sizeof(R) + 15) & ~size_t(15);
   return off + (size_t)(block + 16 * MAXRHS) * sizeof(double);
 }
@@ -376,11 +466,16 @@ static hipError_t launch_hop_t(HopArgs a, int dag, hipStream_t st) {
   a.spb = 256 / inner;
   const int block = (a.spb * inner + 63) & ~63;  // whole waves, <= 256
   a.nblocks = (int)((a.h + a.spb - 1) / a.spb);
-  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block);
-  if (dag)
-    hipLaunchKernelGGL((hop_kernel<P, NS, true>), dim3(a.nblocks), dim3(block), sm, st, a);
-  else
-    hipLaunchKernelGGL((hop_kernel<P, NS, false>), dim3(a.nblocks), dim3(block), sm, st, a);
+  const bool plain = a.prog_h.n == 0 && a.prog_o.n == 0 && a.xin == nullptr && a.partial == nullptr &&
+                     a.c_h == 1.0;
+  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain);
+  if (plain) {
+    if (dag) hipLaunchKernelGGL((hop_kernel<P, NS, true, true>), dim3(a.nblocks), dim3(block), sm, st, a);
+    else hipLaunchKernelGGL((hop_kernel<P, NS, false, true>), dim3(a.nblocks), dim3(block), sm, st, a);
+  } else {
+    if (dag) hipLaunchKernelGGL((hop_kernel<P, NS, true, false>), dim3(a.nblocks), dim3(block), sm, st, a);
+    else hipLaunchKernelGGL((hop_kernel<P, NS, false, false>), dim3(a.nblocks), dim3(block), sm, st, a);
+  }
   return hipGetLastError();
 }
 

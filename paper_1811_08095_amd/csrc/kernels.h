@@ -39,11 +39,17 @@ hipError_t launch_m5(int prec, const void* in, const float* in_sc, void* out, fl
                      int Ns, hipStream_t st);
 
 // BLAS-1 on half fields (blas.hip); n5 = h * nrhs * Ns five-dimensional sites
-hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st);
+// gate / gate_mode (GateMode) restrict the work to selected right-hand sides
+hipError_t launch_vec_zero(int prec, void* v, float* sc, long h, int nrhs, int Ns, hipStream_t st,
+                           const CGScal* gate = nullptr, int gate_mode = GATE_NONE);
 // dst = src (accumulate: dst += src), converting storage precision
 hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc, int prec_dst,
-                              void* dst, float* dst_sc, int accumulate, const int* rhs_mask,
-                              long h, int nrhs, int Ns, hipStream_t st);
+                              void* dst, float* dst_sc, int accumulate, long h, int nrhs, int Ns,
+                              hipStream_t st, const CGScal* gate = nullptr, int gate_mode = GATE_NONE);
+// one right-hand side of a field into one right-hand side of another (zeros if src null)
+hipError_t launch_vec_copy_rhs(int prec_src, const void* src, const float* src_sc, int nrhs_src,
+                               int r_src, int prec_dst, void* dst, float* dst_sc, int nrhs_dst,
+                               int r_dst, long h, int Ns, hipStream_t st);
 // y = x + beta_r y for active right-hand sides
 hipError_t launch_vec_xpby(int prec, const void* x, const float* x_sc, void* y, float* y_sc,
                            const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st);
@@ -54,7 +60,8 @@ int vec_nblocks(long h, int nrhs, int Ns);
 
 // scalar finalisation (blas.hip), one block
 enum FinKind { FIN_SUM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3, FIN_F2 = 4, FIN_TRUE = 5 };
+// gated != 0: only right-hand sides whose update flag is set are finalised
 hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
-                      double* out, hipStream_t st);
+                      double* out, hipStream_t st, int gated = 0);
 
 }  // namespace odwf

@@ -61,8 +61,12 @@ struct CGScal {
   int update;     // reliable update requested
   int iters;      // iterations done
   int maxiter;    // iteration cap
-  int pad[2];
+  int confirm;    // 1: iterated convergence or maxiter requests a true-residual update
+  int nupd;       // true-residual (reliable) updates done
 };
+
+// which right-hand sides a gated kernel works on
+enum GateMode { GATE_NONE = 0, GATE_ACTIVE = 1, GATE_UPDATE = 2 };
 
 struct KappaArr {
   double v[MAXRHS];  // per right-hand side: -mu_r
@@ -95,6 +99,13 @@ struct HopArgs {
   int h, nrhs, spb, out_par, bc_t, dag;
   int L[4];
   int nblocks;
+  // block traversal: xcd != 0 gives each of the 8 XCDs a contiguous range of
+  // logical blocks; tile_y, tile_z > 0 walk (x-row segment, y, z) tiles with t
+  // innermost so that t-neighbours are re-read while still in L2
+  int xcd, tile_y, tile_z;
+  // gating: lanes of right-hand sides not selected by gate_mode do no work
+  const CGScal* gate;
+  int gate_mode;
 };
 
 }  // namespace odwf

@@ -2,6 +2,8 @@
 // hopping-kernel profiler.
 #include "runtime.h"
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace odwf {
@@ -105,6 +107,32 @@ static size_t site_bytes(int prec) {
   return 12 * bytes_per_complex(prec) + ((prec == PREC16 || prec == PRECB16) ? 4 : 0);
 }
 
+// ---- block traversal of the hopping kernel -------------------------------------
+// Defaults: XCD-aware contiguous block ranges, and a t-innermost walk over
+// (y, z) tiles when the x-rows split evenly into blocks.  ODWF_TRAVERSAL
+// ("linear", "xcd", or "Ty,Tz") overrides for tuning.
+static void traversal(HopArgs& a, int Ns) {
+  const int inner = a.nrhs * Ns;
+  const int spb = 256 / inner;
+  const int hx = a.L[0] / 2;
+  a.xcd = 1;
+  a.tile_y = a.tile_z = 0;
+  int ty = 4, tz = 4;
+  const char* env = getenv("ODWF_TRAVERSAL");
+  if (env) {
+    if (!strcmp(env, "linear")) {
+      a.xcd = 0;
+      return;
+    }
+    if (!strcmp(env, "xcd")) return;
+    if (sscanf(env, "%d,%d", &ty, &tz) != 2) return;
+  }
+  if (ty > 0 && tz > 0 && hx % spb == 0 && a.L[1] % ty == 0 && a.L[2] % tz == 0) {
+    a.tile_y = ty;
+    a.tile_z = tz;
+  }
+}
+
 hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out, const HopOpt& o) {
   HopArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -124,6 +152,8 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   a.cg_p_sc = o.cg_p ? o.cg_p->sc : nullptr;
   a.scal = o.scal;
   a.partial = o.partial;
+  a.gate = o.gate;
+  a.gate_mode = o.gate ? o.gate_mode : GATE_NONE;
   a.coef = c.coef();
   for (int r = 0; r < MAXRHS; r++) a.kappa[r] = r < c.nrhs ? c.kappa[r] : 0.0;
   a.prog_h = o.ph;
@@ -137,7 +167,8 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   a.bc_t = L->bc_t;
   a.dag = dag;
   for (int d = 0; d < 4; d++) a.L[d] = L->g.L[d];
-  const bool prof = prof_on();
+  traversal(a, c.S->Ns);
+  const bool prof = prof_on() && !o.gate;  // gated launches do partial work
   if (prof) prof_begin(c.st);
   hipError_t e = launch_hop(a, c.prec, c.S->Ns, c.st);
   if (prof) {

@@ -12,6 +12,12 @@
 #include "kernels.h"
 #include "odwf_types.h"
 
+#define HIPRET(expr)                 \
+  do {                               \
+    hipError_t e_ = (expr);          \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
 namespace odwf {
 
 void set_error(const std::string& msg);
@@ -103,6 +109,9 @@ struct HopOpt {
   HV* cg_x = nullptr;
   const HV* cg_p = nullptr;  // p (mode 2) or f (mode 3)
   const CGScal* scal = nullptr;
+  // gating (GateMode): only right-hand sides selected by gate do any work
+  const CGScal* gate = nullptr;
+  int gate_mode = GATE_NONE;
   HopOpt() : ph(prog_none()), px(prog_none()), po(prog_none()) {}
 };
 

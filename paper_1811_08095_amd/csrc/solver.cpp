@@ -23,12 +23,6 @@
 
 namespace odwf {
 
-#define HIPRET(expr)                   \
-  do {                                 \
-    hipError_t e_ = (expr);            \
-    if (e_ != hipSuccess) return e_;   \
-  } while (0)
-
 hipError_t apply_D(const OpCtx& c, const HV& ie, const HV& io, const HV& te, const HV& to,
                    const HV& oe, const HV& oo) {
   // y = (1 + L) psi; out = omega (A y_site + W y)
@@ -85,9 +79,11 @@ hipError_t apply_schur_dag(const OpCtx& c, const HV& in, const HV& te, const HV&
 }
 
 hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, const HV& out,
-                        double* partial_u, const HopOpt* k4opt) {
+                        double* partial_u, const HopOpt* k4opt, const CGScal* gate, int gate_mode) {
   HopOpt k1;
   k1.ph = prog_ainv();
+  k1.gate = gate;
+  k1.gate_mode = gate_mode;
   HIPRET(hop(c, 1, 0, p, &t, k1));
   HopOpt k2;
   k2.ph = prog_ainv();
@@ -96,18 +92,24 @@ hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, c
   k2.cx = 1.0;
   k2.po = prog_ainv_t();
   k2.partial = partial_u;
+  k2.gate = gate;
+  k2.gate_mode = gate_mode;
   HIPRET(hop(c, 0, 0, t, &v, k2));
   if (partial_u && k4opt && k4opt->scal && k4opt->cg_r)
     HIPRET(launch_fin(FIN_ALPHA, partial_u, hop_nblocks((int)c.h(), c.nrhs, c.Ns()), c.nrhs,
                       const_cast<CGScal*>(k4opt->scal), nullptr, c.st));
   HopOpt k3;
   k3.ph = prog_ainv_t();
+  k3.gate = gate;
+  k3.gate_mode = gate_mode;
   HIPRET(hop(c, 1, 1, v, &t, k3));
   HopOpt k4 = k4opt ? *k4opt : HopOpt();
   k4.x = &v;
   k4.px = prog_a_t();
   k4.ch = -1.0;
   k4.cx = 1.0;
+  k4.gate = gate;
+  k4.gate_mode = gate_mode;
   const HV* o = (k4opt && k4opt->cg_r) ? nullptr : &out;
   return hop(c, 0, 1, t, o, k4);
 }
@@ -269,7 +271,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
   // initial true residual r = f - N y (or r = f from a zero guess)
   auto init_residual = [&](CGScal* sc) -> hipError_t {
     if (use_x0 || outer > 0 || reliable > 0) return true_residual(c64, e0, e1, o0, e2, partial, sc, dres);
-    HIPRET(launch_vec_convert(PREC64, e0.d, nullptr, PREC64, e2.d, nullptr, 0, nullptr, h, nrhs, Ns, st));
+    HIPRET(launch_vec_convert(PREC64, e0.d, nullptr, PREC64, e2.d, nullptr, 0, h, nrhs, Ns, st));
     HIPRET(launch_vec_norm2(PREC64, e2.d, nullptr, partial, h, nrhs, Ns, &nb_vec, st));
     return launch_fin(FIN_INIT, partial, nb_vec, nrhs, sc, dres, st);
   };
@@ -290,8 +292,8 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       return ODWF_ENOMEM;
     }
     CHK(init_residual(dscal));
-    CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, nullptr, h, nrhs, Ns, st));
-    CHK(launch_vec_convert(PREC64, r.d, nullptr, PREC64, p.d, nullptr, 0, nullptr, h, nrhs, Ns, st));
+    CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, h, nrhs, Ns, st));
+    CHK(launch_vec_convert(PREC64, r.d, nullptr, PREC64, p.d, nullptr, 0, h, nrhs, Ns, st));
     CHK(read_scal(dscal, cur, nrhs, st));
     while (any(cur, 0)) {
       for (;;) {
@@ -310,7 +312,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       }
       // confirm with the true residual; continue where it has drifted
       CHK(true_residual(c64, e0, e1, o0, e2, partial, dscal, dres));
-      CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, nullptr, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, h, nrhs, Ns, st));
       CHK(read_scal(dscal, cur, nrhs, st));
       reliable++;
     }
@@ -324,8 +326,8 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       return ODWF_ENOMEM;
     }
     CHK(init_residual(dscal));
-    CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, nullptr, h, nrhs, Ns, st));
-    CHK(launch_vec_convert(inner, rr.d, rr.sc, inner, p.d, p.sc, 0, nullptr, h, nrhs, Ns, st));
+    CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, h, nrhs, Ns, st));
+    CHK(launch_vec_convert(inner, rr.d, rr.sc, inner, p.d, p.sc, 0, h, nrhs, Ns, st));
     CHK(launch_vec_zero(inner, xs.d, xs.sc, h, nrhs, Ns, st));
     CHK(read_scal(dscal, cur, nrhs, st));
     while (any(cur, 0)) {
@@ -344,10 +346,10 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
         if (vw && (!any(vw, 0) || any(vw, 1))) break;
       }
       // reliable update: y += x_s, r = f - N y in FP64, restart the FP32 residual
-      CHK(launch_vec_convert(inner, xs.d, xs.sc, PREC64, e1.d, nullptr, 1, nullptr, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(inner, xs.d, xs.sc, PREC64, e1.d, nullptr, 1, h, nrhs, Ns, st));
       CHK(launch_vec_zero(inner, xs.d, xs.sc, h, nrhs, Ns, st));
       CHK(true_residual(c64, e0, e1, o0, e2, partial, dscal, dres));
-      CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, nullptr, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, h, nrhs, Ns, st));
       CHK(read_scal(dscal, cur, nrhs, st));
       reliable++;
     }
@@ -380,8 +382,8 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
         hin[q].active = cur[q].active;
       }
       CHK(hipMemcpyAsync(dscal, hin, nrhs * sizeof(CGScal), hipMemcpyHostToDevice, st));
-      CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, nullptr, h, nrhs, Ns, st));
-      CHK(launch_vec_convert(inner, rr.d, rr.sc, inner, p.d, p.sc, 0, nullptr, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(inner, rr.d, rr.sc, inner, p.d, p.sc, 0, h, nrhs, Ns, st));
       CHK(launch_vec_zero(inner, xs.d, xs.sc, h, nrhs, Ns, st));
       for (;;) {
         HopOpt k4;
@@ -400,7 +402,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       CGScal fin[MAXRHS];
       CHK(read_scal(dscal, fin, nrhs, st));
       for (int q = 0; q < nrhs; q++) inner_iters[q] += fin[q].iters;
-      CHK(launch_vec_convert(inner, xs.d, xs.sc, PREC64, e1.d, nullptr, 1, nullptr, h, nrhs, Ns, st));
+      CHK(launch_vec_convert(inner, xs.d, xs.sc, PREC64, e1.d, nullptr, 1, h, nrhs, Ns, st));
       outer++;
       // outer residual; carry the iteration count so maxiter bounds the total
       for (int q = 0; q < nrhs; q++) cur[q].iters = inner_iters[q];

@@ -24,7 +24,8 @@ hipError_t apply_schur_dag(const OpCtx& c, const HV& in, const HV& te, const HV&
 // With k4 options the last step can instead update r, x (CG step) or write a
 // residual f - N p.
 hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, const HV& out,
-                        double* partial_u, const HopOpt* k4 = nullptr);
+                        double* partial_u, const HopOpt* k4 = nullptr, const CGScal* gate = nullptr,
+                        int gate_mode = GATE_NONE);
 
 odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double* tol, int r0,
                         int nrhs, int inner, int maxiter, const void* b, void* x, int use_x0,

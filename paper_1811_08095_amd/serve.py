@@ -1,0 +1,233 @@
+"""Serving loop: continuous batching of domain-wall CG solves.
+
+Requests (a lattice, a quark mass, 1-12 right-hand sides, a tolerance) arrive
+as a Poisson stream.  Every resident lattice has one batch engine (libodwf
+odwf_batch_*) with a fixed number of right-hand-side slots, on its own HIP
+stream; gauge fields and solver state stay resident.  The loop
+
+  1. moves arrived requests to their lattice's FIFO queue,
+  2. admits queued requests while their engine has enough free slots and the
+     in-flight HBM footprint stays within the budget,
+  3. enqueues a few CG iterations on every engine that has work (the engines'
+     streams overlap on the device),
+  4. polls the slots, retires finished requests and records their latency
+     (completion - arrival, queueing included).
+
+New requests are admitted between iterations, while earlier ones are still
+iterating: a slot freed by a converged right-hand side is reused at the next
+iteration boundary.  Statistics: p50 / p99 latency, right-hand-side solves per
+second, requests per second.
+"""
+import collections
+import dataclasses
+import json
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    lattice: str
+    mq: float
+    nrhs: int
+    tol: float
+    arrival: float                    # seconds after the stream start
+    seed: int = 0                     # seed of the request's Gaussian sources
+    b: object = None                  # device tensor [nrhs][Ns][t][z][y][x][4][3]
+    slots: List[int] = dataclasses.field(default_factory=list)
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    stats: List[dict] = dataclasses.field(default_factory=list)
+    x: object = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def poisson_stream(n, rate, lattices, masses=(0.005, 0.04, 0.5), nrhs_range=(1, 12),
+                   tols=(1e-8, 1e-10), seed=4):
+    """Arrival times, lattice, mass, right-hand-side count and tolerance of n
+    requests, drawn from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    reqs = []
+    for i in range(n):
+        reqs.append(Request(rid=i, lattice=str(lattices[rng.integers(len(lattices))]),
+                            mq=float(masses[rng.integers(len(masses))]),
+                            nrhs=int(rng.integers(nrhs_range[0], nrhs_range[1] + 1)),
+                            tol=float(tols[rng.integers(len(tols))]), arrival=float(t[i]),
+                            seed=int(seed * 100000 + i)))
+    return reqs
+
+
+def percentile(vals, q):
+    """q-th percentile with linear interpolation (numpy's default)."""
+    return float(np.percentile(np.asarray(vals, dtype=np.float64), q)) if len(vals) else float("nan")
+
+
+class Admission:
+    """Host bookkeeping of slots and in-flight HBM bytes (no GPU calls): a
+    request is admitted when its engine has nrhs free slots and the bytes its
+    slots pin stay within the budget."""
+
+    def __init__(self, slots_per_engine: Dict[str, int], bytes_per_slot: Dict[str, int],
+                 budget_bytes: float):
+        self.free = dict(slots_per_engine)
+        self.bytes_per_slot = dict(bytes_per_slot)
+        self.budget = float(budget_bytes)
+        self.in_flight = 0.0
+
+    def fits(self, req: Request) -> bool:
+        need = req.nrhs * self.bytes_per_slot[req.lattice]
+        return self.free[req.lattice] >= req.nrhs and self.in_flight + need <= self.budget
+
+    def take(self, req: Request):
+        assert self.fits(req)
+        self.free[req.lattice] -= req.nrhs
+        self.in_flight += req.nrhs * self.bytes_per_slot[req.lattice]
+
+    def release(self, req: Request, nslots: int = None):
+        n = req.nrhs if nslots is None else nslots
+        self.free[req.lattice] += n
+        self.in_flight -= n * self.bytes_per_slot[req.lattice]
+
+
+class Server:
+    """Resident lattices with one batch engine each."""
+
+    def __init__(self, lattices: Dict[str, dict], max_slots=12, inner="fp32", hbm_budget=None,
+                 iters_per_step=4, m0=1.3, lmin=0.05, lmax=6.2):
+        import torch
+
+        from . import odwf, synth
+        self.odwf = odwf
+        self.torch = torch
+        self.iters_per_step = int(iters_per_step)
+        inner_p = {"fp32": odwf.FP32, "fp64": odwf.FP64}[inner]
+        self.engines = {}
+        per_slot = {}
+        for name, spec in lattices.items():
+            dims, Ns = tuple(spec["dims"]), int(spec["Ns"])
+            U = synth.make_gauge_device(dims, spec.get("eps", 0.5), spec.get("seed", 0))
+            lat = odwf.Lattice(dims, bc_t=-1)
+            lat.load_gauge(U)
+            del U
+            sol = odwf.Solver(lat, Ns, m0, odwf.zolotarev_omega(Ns, lmin, lmax))
+            stream = torch.cuda.Stream()
+            bt = odwf.Batch(sol, max_slots, inner=inner_p)
+            self.engines[name] = {"lat": lat, "sol": sol, "batch": bt, "stream": stream,
+                                  "dims": dims, "Ns": Ns, "active": []}
+            per_slot[name] = odwf.footprint(dims, Ns, 1, inner_p)
+        torch.cuda.synchronize()
+        budget = hbm_budget if hbm_budget is not None else float("inf")
+        self.admission = Admission({n: max_slots for n in lattices}, per_slot, budget)
+
+    def _admit(self, req: Request, now: float):
+        from . import synth
+        e = self.engines[req.lattice]
+        with self.torch.cuda.stream(e["stream"]):
+            if req.b is None:  # the client's right-hand sides, drawn on arrival
+                req.b = synth.make_source_device(e["dims"], e["Ns"], req.nrhs, req.seed)
+            for r in range(req.nrhs):
+                q = e["batch"].admit(req.b[r], req.mq, req.tol, stream=e["stream"])
+                assert q is not None
+                req.slots.append(q)
+        self.admission.take(req)
+        req.admitted = now
+        e["active"].append(req)
+
+    def run(self, requests: List[Request], time_limit=600.0, keep_solutions=False):
+        """Serve the stream in real time; returns the finished requests."""
+        torch = self.torch
+        queues = collections.defaultdict(collections.deque)
+        pending = sorted(requests, key=lambda r: r.arrival)
+        done: List[Request] = []
+        pi = 0
+        t0 = time.perf_counter()
+        while len(done) < len(requests):
+            now = time.perf_counter() - t0
+            if now > time_limit:
+                break
+            while pi < len(pending) and pending[pi].arrival <= now:
+                queues[pending[pi].lattice].append(pending[pi])
+                pi += 1
+            for name, q in queues.items():
+                while q and self.admission.fits(q[0]):
+                    self._admit(q.popleft(), now)
+            busy = [e for e in self.engines.values() if e["active"]]
+            if not busy:
+                if pi < len(pending):
+                    time.sleep(min(0.002, max(0.0, pending[pi].arrival - now)))
+                continue
+            for e in busy:
+                e["batch"].step(self.iters_per_step, stream=e["stream"])
+            for e in busy:
+                still = []
+                for req in e["active"]:
+                    fin = True
+                    for q in req.slots:
+                        d, _ = e["batch"].poll(q, stream=e["stream"])
+                        fin &= d
+                    if not fin:
+                        still.append(req)
+                        continue
+                    out = torch.empty_like(req.b) if keep_solutions else torch.empty_like(req.b[0])
+                    for i, q in enumerate(req.slots):
+                        st = e["batch"].retire(q, out[i] if keep_solutions else out,
+                                               stream=e["stream"])
+                        req.stats.append(st)
+                    req.x = out if keep_solutions else None
+                    req.finished = time.perf_counter() - t0
+                    self.admission.release(req)
+                    req.b = None
+                    done.append(req)
+                e["active"] = still
+        return done
+
+
+def summarize(done: List[Request], makespan: float):
+    lat = [r.latency for r in done]
+    nrhs = sum(r.nrhs for r in done)
+    resid_ok = all(s["true_rel_resid"] <= r.tol and s["status"] == 0 for r in done for s in r.stats)
+    return {"requests": len(done), "rhs": nrhs, "makespan_s": round(makespan, 3),
+            "p50_latency_s": round(percentile(lat, 50), 4), "p99_latency_s": round(percentile(lat, 99), 4),
+            "rhs_solves_per_s": round(nrhs / makespan, 3) if makespan > 0 else None,
+            "requests_per_s": round(len(done) / makespan, 3) if makespan > 0 else None,
+            "all_converged": bool(resid_ok)}
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="serve a Poisson stream of ODWF solve requests")
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--rate", type=float, default=0.0, help="arrivals/s (0: measure saturation)")
+    ap.add_argument("--load", type=float, default=0.8, help="fraction of saturation throughput")
+    ap.add_argument("--sizes", default="8,16,24")
+    ap.add_argument("--Ns", type=int, default=16)
+    ap.add_argument("--max-slots", type=int, default=12)
+    ap.add_argument("--inner", default="fp32")
+    args = ap.parse_args()
+    lattices = {f"{L}^4": {"dims": (L, L, L, L), "Ns": args.Ns, "eps": 0.5, "seed": 0}
+                for L in (int(v) for v in args.sizes.split(","))}
+    srv = Server(lattices, max_slots=args.max_slots, inner=args.inner)
+    rate = args.rate
+    if rate <= 0:  # saturation: everything arrives at once
+        warm = poisson_stream(min(24, args.requests), 1e9, list(lattices), seed=3)
+        t = time.perf_counter()
+        d = srv.run(warm)
+        sat = len(d) / (time.perf_counter() - t)
+        rate = args.load * sat
+    reqs = poisson_stream(args.requests, rate, list(lattices))
+    t = time.perf_counter()
+    done = srv.run(reqs)
+    out = summarize(done, time.perf_counter() - t)
+    out["arrival_rate"] = round(rate, 3)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
