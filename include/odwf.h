@@ -211,6 +211,12 @@ void odwf_batch_destroy(odwf_batch bt);
 odwf_status odwf_profile_enable(int enable);
 odwf_status odwf_profile_read(long long* launches, double* ms, double* bytes);
 
+/* The same counters restricted to one instantiation of the hopping kernel:
+ * storage precision `prec` and dag = 0 (W, forward projector 1 - gamma) or
+ * dag = 1 (W^dag). */
+odwf_status odwf_profile_read_kernel(odwf_prec prec, int dag, long long* launches, double* ms,
+                                     double* bytes);
+
 /* Thread-local message describing the last error of the calling thread. */
 const char* odwf_last_error(void);
 

@@ -19,6 +19,7 @@ namespace odwf {
 const char* last_error_cstr();
 void prof_enable(int on);
 void prof_read(long long* launches, double* ms, double* bytes);
+void prof_read_kernel(int prec, int dag, long long* launches, double* ms, double* bytes);
 }  // namespace odwf
 
 #define HIPCHK(expr)                                                               \
@@ -392,6 +393,13 @@ extern "C" odwf_status odwf_profile_enable(int enable) {
 
 extern "C" odwf_status odwf_profile_read(long long* launches, double* ms, double* bytes) {
   prof_read(launches, ms, bytes);
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_profile_read_kernel(odwf_prec prec, int dag, long long* launches,
+                                                double* ms, double* bytes) {
+  REQUIRE(prec >= ODWF_FP64 && prec <= ODWF_BF16S, "odwf_profile_read_kernel: bad precision");
+  prof_read_kernel((int)prec, dag, launches, ms, bytes);
   return ODWF_OK;
 }
 

@@ -108,7 +108,7 @@ extern "C" odwf_status odwf_batch_create(odwf_solver S, int max_slots, odwf_prec
   B->s_o0 = W.half("s_o0", h, 1, Ns, PREC64);
   B->s_bo = W.half("s_bo", h, 1, Ns, PREC64);
   const int nb = std::max(hop_nblocks((int)h, k, Ns), vec_nblocks(h, k, Ns));
-  B->partial = (double*)W.get("partial", (size_t)nb * k * sizeof(double));
+  B->partial = (double*)W.get("partial", partial_bytes(nb, k));
   B->dscal = (CGScal*)W.get("scal", MAXRHS * sizeof(CGScal));
   B->dres = (double*)W.get("res", 4 * MAXRHS * sizeof(double));
   bool ok = B->f.d && B->y.d && B->e2.d && B->o0.d && B->bo.d && B->p.d && B->r.d && B->t.d &&

@@ -316,8 +316,41 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
   scal[r] = c;
 }
 
+// first stage of the finalisation for long partial arrays: block b sums the
+// partials of blocks [b * 1024, (b + 1) * 1024) per right-hand side in a fixed
+// tree and writes them to dst[b * nrhs + r]
+__global__ void partial_reduce_kernel(const double* partial, int nblocks, int nrhs, double* dst) {
+  __shared__ double red[256];
+  const int b0 = blockIdx.x * 1024;
+  const int b1 = min(b0 + 1024, nblocks);
+  for (int r = 0; r < nrhs; r++) {
+    double acc = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) acc += partial[(long)b * nrhs + r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) dst[(long)blockIdx.x * nrhs + r] = red[0];
+    __syncthreads();
+  }
+}
+
+size_t partial_bytes(int nblocks, int nrhs) {
+  return ((size_t)nblocks + (nblocks + 1023) / 1024 + 16) * nrhs * sizeof(double);
+}
+
 hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
                       double* out, hipStream_t st, int gated) {
+  if (nblocks > 2048) {
+    // two stages; the second-stage inputs live behind the first-stage partials
+    double* dst = const_cast<double*>(partial) + (size_t)nblocks * nrhs;
+    const int nb2 = (nblocks + 1023) / 1024;
+    hipLaunchKernelGGL(partial_reduce_kernel, dim3(nb2), dim3(256), 0, st, partial, nblocks, nrhs, dst);
+    partial = dst;
+    nblocks = nb2;
+  }
   hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, st, kind, partial, nblocks, nrhs, scal, out,
                      gated);
   return hipGetLastError();

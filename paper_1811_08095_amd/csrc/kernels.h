@@ -60,6 +60,9 @@ int vec_nblocks(long h, int nrhs, int Ns);
 
 // scalar finalisation (blas.hip), one block
 enum FinKind { FIN_SUM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3, FIN_F2 = 4, FIN_TRUE = 5 };
+// bytes a partial-sum buffer for nblocks blocks needs (includes the second
+// reduction stage used for long partial arrays)
+size_t partial_bytes(int nblocks, int nrhs);
 // gated != 0: only right-hand sides whose update flag is set are finalised
 hipError_t launch_fin(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
                       double* out, hipStream_t st, int gated = 0);

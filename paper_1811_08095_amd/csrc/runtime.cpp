@@ -169,7 +169,7 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   for (int d = 0; d < 4; d++) a.L[d] = L->g.L[d];
   traversal(a, c.S->Ns);
   const bool prof = prof_on() && !o.gate;  // gated launches do partial work
-  if (prof) prof_begin(c.st);
+  if (prof) prof_begin(c.st, (c.prec & 3) * 2 + (dag ? 1 : 0));
   hipError_t e = launch_hop(a, c.prec, c.S->Ns, c.st);
   if (prof) {
     const double n5 = (double)L->g.h * c.nrhs * c.S->Ns;
@@ -195,6 +195,7 @@ hipError_t m5(const OpCtx& c, const HV& in, const HV& out, const M5Prog& p, doub
 struct ProfRec {
   hipEvent_t a, b;
   double bytes;
+  int key;  // prec * 2 + dag
 };
 static std::mutex g_prof_mtx;
 static bool g_prof = false;
@@ -203,6 +204,9 @@ static std::vector<hipEvent_t> g_pool;
 static thread_local hipEvent_t g_open = nullptr;
 static long long g_launches = 0;
 static double g_ms = 0.0, g_bytes = 0.0;
+static long long g_k_launches[8] = {0};
+static double g_k_ms[8] = {0}, g_k_bytes[8] = {0};
+static thread_local int g_open_key = 0;
 
 bool prof_on() { return g_prof; }
 
@@ -225,15 +229,19 @@ static void drain_locked() {
     g_ms += ms;
     g_bytes += r.bytes;
     g_launches += 1;
+    g_k_ms[r.key] += ms;
+    g_k_bytes[r.key] += r.bytes;
+    g_k_launches[r.key] += 1;
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }
   g_recs.clear();
 }
 
-void prof_begin(hipStream_t st) {
+void prof_begin(hipStream_t st, int key) {
   std::lock_guard<std::mutex> lk(g_prof_mtx);
   if (g_recs.size() > 4096) drain_locked();
+  g_open_key = key;
   g_open = take_event();
   (void)hipEventRecord(g_open, st);
 }
@@ -242,7 +250,7 @@ void prof_end(hipStream_t st, double bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mtx);
   hipEvent_t b = take_event();
   (void)hipEventRecord(b, st);
-  g_recs.push_back(ProfRec{g_open, b, bytes});
+  g_recs.push_back(ProfRec{g_open, b, bytes, g_open_key});
   g_open = nullptr;
 }
 
@@ -253,6 +261,10 @@ void prof_enable(int on) {
   g_launches = 0;
   g_ms = 0.0;
   g_bytes = 0.0;
+  for (int k = 0; k < 8; k++) {
+    g_k_launches[k] = 0;
+    g_k_ms[k] = g_k_bytes[k] = 0.0;
+  }
 }
 
 void prof_read(long long* launches, double* ms, double* bytes) {
@@ -261,6 +273,15 @@ void prof_read(long long* launches, double* ms, double* bytes) {
   if (launches) *launches = g_launches;
   if (ms) *ms = g_ms;
   if (bytes) *bytes = g_bytes;
+}
+
+void prof_read_kernel(int prec, int dag, long long* launches, double* ms, double* bytes) {
+  std::lock_guard<std::mutex> lk(g_prof_mtx);
+  drain_locked();
+  const int key = (prec & 3) * 2 + (dag ? 1 : 0);
+  if (launches) *launches = g_k_launches[key];
+  if (ms) *ms = g_k_ms[key];
+  if (bytes) *bytes = g_k_bytes[key];
 }
 
 }  // namespace odwf

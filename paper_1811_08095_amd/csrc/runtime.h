@@ -120,7 +120,7 @@ hipError_t m5(const OpCtx& c, const HV& in, const HV& out, const M5Prog& p, doub
               const HV* other = nullptr, double c1 = 0.0);
 
 // profiler hooks
-void prof_begin(hipStream_t st);
+void prof_begin(hipStream_t st, int key);
 void prof_end(hipStream_t st, double bytes);
 bool prof_on();
 

@@ -162,7 +162,7 @@ size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner) {
     b += 5 * (half_bytes(h, nrhs, Ns, inner) + scale_bytes(h, nrhs, Ns, inner));
   }
   const int nb = std::max(hop_nblocks((int)h, nrhs, Ns), vec_nblocks(h, nrhs, Ns));
-  b += (size_t)nb * nrhs * sizeof(double) + 64 * 1024;
+  b += partial_bytes(nb, nrhs) + 64 * 1024;
   return b;
 }
 
@@ -209,7 +209,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
   HV e2 = W.half("s.e2", h, nrhs, Ns, PREC64);  // FP64 even scratch / residual
   HV o0 = W.half("s.o0", h, nrhs, Ns, PREC64);  // FP64 odd scratch
   const int nbmax = std::max(hop_nblocks((int)h, nrhs, Ns), vec_nblocks(h, nrhs, Ns));
-  double* partial = (double*)W.get("s.partial", (size_t)nbmax * nrhs * sizeof(double));
+  double* partial = (double*)W.get("s.partial", partial_bytes(nbmax, nrhs));
   CGScal* dscal = (CGScal*)W.get("s.scal", 2 * MAXRHS * sizeof(CGScal));
   CGScal* dscal_out = dscal + MAXRHS;
   double* dres = (double*)W.get("s.res", 4 * MAXRHS * sizeof(double));

@@ -69,6 +69,7 @@ SYMBOLS = {
     "odwf_batch_destroy": ([_vp], None),
     "odwf_profile_enable": ([_i], _i),
     "odwf_profile_read": ([ctypes.POINTER(ctypes.c_longlong), _dp, _dp], _i),
+    "odwf_profile_read_kernel": ([_i, _i, ctypes.POINTER(ctypes.c_longlong), _dp, _dp], _i),
     "odwf_last_error": ([], ctypes.c_char_p),
     "odwf_version": ([], ctypes.c_char_p),
 }
@@ -150,6 +151,17 @@ def profile_read():
     ms = ctypes.c_double()
     by = ctypes.c_double()
     _check(lib().odwf_profile_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def profile_read_kernel(prec, dag):
+    """(launches, milliseconds, algorithmic bytes) of one hopping-kernel
+    instantiation: storage precision prec, dag 0 (W) or 1 (W^dag)."""
+    n = ctypes.c_longlong()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(lib().odwf_profile_read_kernel(int(prec), int(dag), ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(by)))
     return n.value, ms.value, by.value
 
 
