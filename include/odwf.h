@@ -16,7 +16,7 @@
  * hops across the t boundary multiplied by bc_t.  Even-odd form (not in the
  * paper; the standard Schur complement on even sites, unit-diagonal form):
  *     W = D_w - (4 - m0),  A = (4 - m0) + omega^{-1} (1 - L)(1 + L)^{-1},
- *     S_e = 1 - A^{-1} W_eo A^{-1} W_oe,   CG on S_e^dag S_e (§2: "conjugate gradient").
+ *     S_e = 1 - A^{-1} W_eo A^{-1} W_oe, and conjugate gradient on S_e^dag S_e (§2).
  *
  * Conventions shared by every entry point
  *   - gamma matrices: chiral basis gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
@@ -37,10 +37,10 @@
  *   - Errors: every call returns an odwf_status; no exception or abort crosses
  *     the ABI; odwf_last_error() gives a thread-local message for the last
  *     failing call of the calling thread.
- *   - Threads: handles are immutable after creation except batches; different
- *     threads may use one solver concurrently on different streams, except
- *     that odwf_solve calls on one solver are serialised (its workspaces are
- *     shared; a second concurrent call waits).
+ *   - Threads: handles are immutable after creation except batches.  Calls on
+ *     one solver from several threads are serialised by a lock; the solver
+ *     keeps its workspaces per stream, so calls on different streams never
+ *     share a buffer.  A batch is used from one thread at a time.
  */
 #ifndef ODWF_H
 #define ODWF_H
