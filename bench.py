@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 CG comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="16,16,16,16")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (the reference dispatch "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters under rocprofv3)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -101,6 +104,17 @@ def main():
     dev = torch.device("cuda:0")
     free0, total = torch.cuda.mem_get_info()
     print(f"# device memory: free {free0/1e9:.1f} GB of {total/1e9:.1f} GB", file=sys.stderr, flush=True)
+
+    if args.copy_calibration_gib > 0:
+        nb = int(args.copy_calibration_gib * (1 << 30))
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nb} bytes device to device", file=sys.stderr, flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
 
     t0 = time.time()
     U = synth.make_gauge_device(dims, args.eps, 0)
@@ -148,6 +162,12 @@ def main():
 
     gbs = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     avg_ms = kms / max(launches, 1)
+    # HBM-side traffic per launch of the same kernel, from the committed counter
+    # summary of this workload, when it was taken on the current kernel sources
+    from paper_1811_08095_amd import profsum
+    wkey = f"{'x'.join(map(str, dims))}_Ns{Ns}_{args.inner}_mq{masses[0]}"
+    traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", f"hop_kernel_{wkey}_traffic.md"), wkey)
+    traffic = round(traffic, 4) if traffic is not None else None
     result = {
         "metric": "EO-ODWF Dslash HBM GB/s; solves/s at 1e-10 resid, mixed vs FP64; p99 latency",
         "value": round(gbs, 1),
@@ -176,10 +196,11 @@ def main():
                       "gauge_resident": round(lat.nbytes() / 1e9, 2),
                       "solver_workspace_est": round(odwf.footprint(dims, Ns, 1, inner) / 1e9, 2)},
         "roofline": {"bound": "hbm", "achieved": round(dk_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dk_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(dk_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_gb_per_launch": round(dk_by / max(dk_n, 1) / 1e9, 4),
                      "kernel": f"hop_kernel<{args.inner}, Ns={Ns}> (W and W^dag instantiations, "
-                               f"{dk_n} launches, avg {dk_ms / max(dk_n, 1):.3f} ms, "
-                               f"{dk_by / max(dk_n, 1) / 1e9:.2f} GB algorithmic per launch)"},
+                               f"{dk_n} launches, avg {dk_ms / max(dk_n, 1):.3f} ms)"},
     }
     if not args.no_fp64_compare:
         # a fresh solver: the mixed-precision workspaces are released first, so

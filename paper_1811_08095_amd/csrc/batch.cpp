@@ -101,7 +101,7 @@ extern "C" odwf_status odwf_batch_create(odwf_solver S, int max_slots, odwf_prec
   B->r = W.half("r", h, k, Ns, inner);
   B->t = W.half("t", h, k, Ns, inner);
   B->v = W.half("v", h, k, Ns, inner);
-  if (inner != PREC64) B->x = W.half("x", h, k, Ns, inner);
+  if ((int)inner != PREC64) B->x = W.half("x", h, k, Ns, inner);
   B->s_e0 = W.half("s_e0", h, 1, Ns, PREC64);
   B->s_e1 = W.half("s_e1", h, 1, Ns, PREC64);
   B->s_e2 = W.half("s_e2", h, 1, Ns, PREC64);
@@ -112,7 +112,7 @@ extern "C" odwf_status odwf_batch_create(odwf_solver S, int max_slots, odwf_prec
   B->dscal = (CGScal*)W.get("scal", MAXRHS * sizeof(CGScal));
   B->dres = (double*)W.get("res", 4 * MAXRHS * sizeof(double));
   bool ok = B->f.d && B->y.d && B->e2.d && B->o0.d && B->bo.d && B->p.d && B->r.d && B->t.d &&
-            B->v.d && (inner == PREC64 || B->x.d) && B->s_e0.d && B->s_e1.d && B->s_e2.d &&
+            B->v.d && ((int)inner == PREC64 || B->x.d) && B->s_e0.d && B->s_e1.d && B->s_e2.d &&
             B->s_o0.d && B->s_bo.d && B->partial && B->dscal && B->dres;
   if (ok && hipHostMalloc((void**)&B->hscal, MAXRHS * sizeof(CGScal), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();

@@ -100,7 +100,7 @@ __global__ void vec_norm2_kernel(const void* v, const float* sc, double* partial
     }
   red[threadIdx.x] = acc;
   block_reduce_rhs(
-      red, blockDim.x, nrhs, [&](int k) { return (k % inner) / Ns; }, red + 1024, partial);
+      red, blockDim.x, nrhs, [&](int k) { return (k % inner) / Ns; }, red + 1024, partial, blockIdx.x);
 }
 
 #define ODWF_PREC_SWITCH(prec, KERNEL, ...)                                             \

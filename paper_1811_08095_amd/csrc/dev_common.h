@@ -204,6 +204,28 @@ __device__ __forceinline__ void load_site_cached(const void* base, const float* 
   }
 }
 
+// load of site (row + xi): the row's first site `row` is the same for the
+// whole block (a uniform 64-bit base), the position xi in the row is per lane
+// (a 32-bit offset), which keeps the address arithmetic out of vector registers
+template <class P>
+__device__ __forceinline__ void load_site_row(const void* base, const float* scale, long row, int xi,
+                                              int r, int s, int nrhs, int Ns,
+                                              cpx<typename P::real> (&v)[12]) {
+  constexpr int NCG = 12 / P::CPB;
+  const uint4* b = reinterpret_cast<const uint4*>(base) + row * (long)(nrhs * NCG * Ns);
+  const int off = ((xi * nrhs + r) * NCG) * Ns + s;
+  uint4 q[NCG];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
+  if constexpr (P::SCALED) {
+    const float sc = scale[row * (long)(nrhs * Ns) + (xi * nrhs + r) * Ns + s];
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = cscale(sc, v[c]);
+  }
+}
+
 template <class P>
 __device__ __forceinline__ void store_site(void* base, float* scale, long j, int r, int s, int nrhs,
                                            int Ns, const cpx<typename P::real> (&v)[12]) {
@@ -344,11 +366,11 @@ __device__ __forceinline__ void column_pass_lds(cpx<R>* buf, int nsb, int nrhs, 
 // ---------------------------------------------------------------------------
 // deterministic per-right-hand-side block reduction
 // vals[k] (k < count) in LDS, key(k) gives the right-hand side of entry k.
-// Writes partial[blockIdx.x * nrhs + r].  All threads must call.
+// Writes partial[slot * nrhs + r].  All threads must call.
 // ---------------------------------------------------------------------------
 template <class KeyF>
 __device__ void block_reduce_rhs(double* vals, int count, int nrhs, KeyF key, double* tmp,
-                                 double* partial) {
+                                 double* partial, long slot) {
   __syncthreads();
   const int tid = threadIdx.x;
   if (tid < nrhs * 16) {
@@ -363,7 +385,7 @@ __device__ void block_reduce_rhs(double* vals, int count, int nrhs, KeyF key, do
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; q++) acc += tmp[tid * 16 + q];
-    partial[(long)blockIdx.x * nrhs + tid] = acc;
+    partial[slot * nrhs + tid] = acc;
   }
 }
 

@@ -206,11 +206,15 @@ __device__ __forceinline__ long block_first_site(const HopArgs& a) {
     rest /= a.tile_y;
     const int zi = rest % a.tile_z;
     rest /= a.tile_z;
-    const int t = rest % a.L[3];
-    rest /= a.L[3];
-    const int nty = a.L[1] / a.tile_y;
+    const int tlen = a.tile_t > 0 ? a.tile_t : a.L[3];
+    const int tl = rest % tlen;
+    rest /= tlen;
+    const int nty = a.L[1] / a.tile_y, ntz = a.L[2] / a.tile_z;
     const int y = (rest % nty) * a.tile_y + yi;
-    const int z = (rest / nty) * a.tile_z + zi;
+    rest /= nty;
+    const int z = (rest % ntz) * a.tile_z + zi;
+    rest /= ntz;
+    const int t = rest * tlen + tl;  // rest: index of the t chunk
     return (((long)t * a.L[2] + z) * a.L[1] + y) * hx + (long)seg * a.spb;
   }
   return (long)lb * a.spb;
@@ -229,6 +233,110 @@ template <class P>
 struct HopGroup {
   static constexpr int G = sizeof(typename P::real) == 8 ? ODWF_HOP_GROUP64 : ODWF_HOP_GROUP32;
 };
+
+// x term of the fused epilogue: already transformed in the column buffer, or
+// loaded here (and transformed here when it has a fifth-dimension program)
+enum XMode { X_LDS = 1, X_LOAD = 2 };
+
+// Fused epilogue of one output site after the hop: the fifth-dimension column
+// passes, the x term, the norm for the partial sums, and the residual, the CG
+// update or the store.  Every thread of the block calls it (the column passes
+// synchronise the block); returns this lane's share of the partial sum.
+template <class P, int NS>
+__device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::real> (&acc)[12], bool valid,
+                                             long j, int sl, int r, int s, int nsb,
+                                             cpx<typename P::real>* buf, const typename P::real* coef,
+                                             const typename P::real* kap, int xmode) {
+  using R = typename P::real;
+  constexpr int NSP = NS + 1;
+  const int nrhs = a.nrhs;
+  auto column_pass = [&](const M5Prog& prog, cpx<R>(&v)[12]) {
+    __syncthreads();
+    if (valid) {
+      cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
+#pragma unroll
+      for (int c = 0; c < 12; c++) b[c * NSP] = v[c];
+    }
+    __syncthreads();
+    column_pass_lds<R, NS>(buf, nsb, nrhs, prog, coef, kap);
+    __syncthreads();
+    if (valid) {
+      const cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
+#pragma unroll
+      for (int c = 0; c < 12; c++) v[c] = b[c * NSP];
+    }
+  };
+
+  if (a.prog_h.n > 0) column_pass(a.prog_h, acc);  // never together with X_LDS
+  cpx<R> xv[12];
+  const bool has_x = a.xin != nullptr;
+  if (has_x) {
+    if (xmode == X_LDS) {  // transformed before the hop, still in the column buffer
+      if (valid) {
+        const cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
+#pragma unroll
+        for (int c = 0; c < 12; c++) xv[c] = b[c * NSP];
+      }
+    } else {
+      if (valid) load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+      if (a.prog_x.n > 0) column_pass(a.prog_x, xv);
+    }
+  }
+  if (has_x) {
+    const R ch = (R)a.c_h, cx = (R)a.c_x;
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = cadd(cscale(ch, acc[c]), cscale(cx, xv[c]));
+  } else if (a.c_h != 1.0) {
+    const R ch = (R)a.c_h;
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = cscale(ch, acc[c]);
+  }
+
+  const int cgmode = a.partial ? (a.cg_r ? 2 : (a.cg_p ? 3 : 1)) : 0;
+  double nval = 0.0;
+  if (cgmode == 1 && valid) {
+#pragma unroll
+    for (int c = 0; c < 12; c++) nval += (double)cnorm2(acc[c]);
+  }
+  if (a.prog_o.n > 0) column_pass(a.prog_o, acc);
+
+  if (cgmode == 3 && valid) {  // residual: out = f - y
+    cpx<R> f[12];
+    load_site<P>(a.cg_p, a.cg_p_sc, j, r, s, nrhs, NS, f);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+      acc[c] = csub(f[c], acc[c]);
+      nval += (double)cnorm2(acc[c]);
+    }
+  }
+  if (cgmode == 2) {
+    if (valid && a.scal[r].active) {
+      const R al = (R)a.scal[r].alpha;
+      {  // r -= alpha N p, |r|^2
+        cpx<R> rv[12];
+        load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+          rv[c] = csub(rv[c], cscale(al, acc[c]));
+          nval += (double)cnorm2(rv[c]);
+        }
+        store_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+      }
+      {  // x += alpha p
+        cpx<R> xx[12], pv[12];
+        load_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
+        load_site<P>(a.cg_p, a.cg_p_sc, j, r, s, nrhs, NS, pv);
+#pragma unroll
+        for (int c = 0; c < 12; c++) xx[c] = cadd(xx[c], cscale(al, pv[c]));
+        store_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
+      }
+    }
+  } else if (valid && a.out) {
+    store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+  }
+
+  return nval;
+}
 
 // minimum waves per SIMD the register allocation must allow
 template <class P, bool PLAIN>
@@ -361,99 +469,241 @@ __global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const
     return;
   }
 
-  // ---- fifth-dimension column passes --------------------------------------
-  auto column_pass = [&](const M5Prog& prog, cpx<R>(&v)[12]) {
-    __syncthreads();
-    if (valid) {
-      cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
-#pragma unroll
-      for (int c = 0; c < 12; c++) b[c * NSP] = v[c];
-    }
-    __syncthreads();
-    column_pass_lds<R, NS>(buf, nsb, nrhs, prog, coef, kap);
-    __syncthreads();
-    if (valid) {
-      const cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
-#pragma unroll
-      for (int c = 0; c < 12; c++) v[c] = b[c * NSP];
-    }
-  };
-
-  if (a.prog_h.n > 0) column_pass(a.prog_h, acc);  // never together with x_first
-  if (has_x && valid) {
-    if (x_first) {
-      const cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
-#pragma unroll
-      for (int c = 0; c < 12; c++) xv[c] = b[c * NSP];
-    } else {
-      load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
-    }
-  }
-  if (has_x) {
-    const R ch = (R)a.c_h, cx = (R)a.c_x;
-#pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = cadd(cscale(ch, acc[c]), cscale(cx, xv[c]));
-  } else if (a.c_h != 1.0) {
-    const R ch = (R)a.c_h;
-#pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = cscale(ch, acc[c]);
-  }
-
-  const int cgmode = a.partial ? (a.cg_r ? 2 : (a.cg_p ? 3 : 1)) : 0;
-  double nval = 0.0;
-  if (cgmode == 1 && valid) {
-#pragma unroll
-    for (int c = 0; c < 12; c++) nval += (double)cnorm2(acc[c]);
-  }
-  if (a.prog_o.n > 0) column_pass(a.prog_o, acc);
-
-  if (cgmode == 3 && valid) {  // residual: out = f - y
-    cpx<R> f[12];
-    load_site<P>(a.cg_p, a.cg_p_sc, j, r, s, nrhs, NS, f);
-#pragma unroll
-    for (int c = 0; c < 12; c++) {
-      acc[c] = csub(f[c], acc[c]);
-      nval += (double)cnorm2(acc[c]);
-    }
-  }
-  if (cgmode == 2) {
-    if (valid && a.scal[r].active) {
-      const R al = (R)a.scal[r].alpha;
-      {  // r -= alpha N p, |r|^2
-        cpx<R> rv[12];
-        load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-          rv[c] = csub(rv[c], cscale(al, acc[c]));
-          nval += (double)cnorm2(rv[c]);
-        }
-        store_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
-      }
-      {  // x += alpha p
-        cpx<R> xx[12], pv[12];
-        load_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
-        load_site<P>(a.cg_p, a.cg_p_sc, j, r, s, nrhs, NS, pv);
-#pragma unroll
-        for (int c = 0; c < 12; c++) xx[c] = cadd(xx[c], cscale(al, pv[c]));
-        store_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
-      }
-    }
-  } else if (valid && a.out) {
-    store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
-  }
-
-  if (cgmode) {
+  const double nval =
+      fused_tail<P, NS>(a, acc, valid, j, sl, r, s, nsb, buf, coef, kap, x_first ? X_LDS : X_LOAD);
+  if (a.partial) {
     red[tid] = valid ? nval : 0.0;
     block_reduce_rhs(
-        red, blockDim.x, nrhs, [&](int k) { return (k % inner) / NS; }, rtmp, a.partial);
+        red, blockDim.x, nrhs, [&](int k) { return (k % inner) / NS; }, rtmp, a.partial, blockIdx.x);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// t-sweep hopping kernel.  Block b owns the output sites of one x-row segment
+// (seg, y, z) for t in [t0, t0 + sweep) and walks them in t.  The input
+// spinor of the block's own column at t is carried from step to step in
+// registers: it is the x-hop input at step t (one of the two x neighbours of
+// every output site lies in the own column, the other in the adjacent lane,
+// exchanged through LDS), the +t neighbour at step t - 1 and, as its projected
+// half spinor, the -t neighbour at step t + 1.  Each input row of the column is
+// therefore read from memory once per sweep instead of three times; the y and
+// z neighbours are the own columns of concurrently running blocks and are
+// read while they are still in L2.  The epilogue of every step is the one of
+// the one-t-per-block kernel.
+// ---------------------------------------------------------------------------
+#ifndef ODWF_SWEEP_WAVES_PLAIN
+#define ODWF_SWEEP_WAVES_PLAIN 4
+#endif
+// minimum waves per SIMD of the t-sweep kernel (its column state costs registers)
+template <class P, bool PLAIN>
+struct SweepWaves {
+  static constexpr int W = sizeof(typename P::real) == 8 ? (PLAIN ? 2 : 1) : (PLAIN ? ODWF_SWEEP_WAVES_PLAIN : 2);
+};
+
+template <class P, int NS, bool DAG, bool PLAIN>
+__global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kernel(const HopArgs a) {
+  using R = typename P::real;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nrhs = a.nrhs;
+  const int inner = nrhs * NS;
+  const int tid = threadIdx.x;
+  const int sl = tid / inner;
+  const int lr = tid - sl * inner;
+  const int r = lr / NS;
+  const int s = lr - r * NS;
+  if (!gate_any(a.gate, a.gate_mode, nrhs)) {
+    // idle block: its partial-sum slots still have to read zero
+    if (a.partial && tid < nrhs) {
+      a.partial[(long)blockIdx.x * nrhs + tid] = 0.0;
+      for (int k = 1; k < a.sweep; k++)
+        a.partial[((long)gridDim.x + (long)blockIdx.x * (a.sweep - 1) + (k - 1)) * nrhs + tid] = 0.0;
+    }
+    return;
+  }
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int hx = L0 >> 1;
+  const int spb = a.spb;
+  const int nseg = hx / spb;
+
+  // block -> (segment, y, z, first t): XCD-aware ranges, (y, z) tiles, t chunks slowest
+  int lb = blockIdx.x;
+  if (a.xcd) {
+    const int q = a.nblocks >> 3, rem = a.nblocks & 7;
+    const int xc = lb & 7, k = lb >> 3;
+    lb = xc * q + min(xc, rem) + k;
+  }
+  const int ty = a.tile_y > 0 ? a.tile_y : 1, tz = a.tile_z > 0 ? a.tile_z : 1;
+  const int seg = lb % nseg;
+  lb /= nseg;
+  const int yi = lb % ty;
+  lb /= ty;
+  const int zi = lb % tz;
+  lb /= tz;
+  const int nty = L1 / ty, ntz = L2 / tz;
+  const int y = (lb % nty) * ty + yi;
+  lb /= nty;
+  const int z = (lb % ntz) * tz + zi;
+  lb /= ntz;
+  const int t0 = lb * a.sweep;
+
+  // padded threads have sl >= spb; gated-off right-hand sides do no work
+  const bool valid = sl < spb && gate_on(a.gate, a.gate_mode, r);
+  const int xh = seg * spb + sl;  // half-row index of this lane's output and own input column
+  constexpr int NSP = NS + 1;
+
+  // LDS: links, the x-exchange buffer (spb + 2 sites: the segment and one
+  // halo site on each side) aliased with the column buffer, kappa, reduction scratch
+  const size_t lnk_n = (size_t)spb * 8 * 9;
+  const int xstride = (spb + 2) * inner;  // per component
+  const size_t xch_n = (size_t)12 * xstride;
+  const size_t col_n = (size_t)spb * nrhs * 12 * NSP;
+  const size_t buf_n = PLAIN || xch_n > col_n ? xch_n : col_n;
+  cpx<R>* lnk = reinterpret_cast<cpx<R>*>(smem);
+  cpx<R>* buf = lnk + lnk_n;
+  const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
+  R* kap = reinterpret_cast<R*>(smem + region);
+  double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
+  double* rtmp = red + blockDim.x;
+  const R* coef = reinterpret_cast<const R*>(a.coef);
+  if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
+
+  auto row = [&](int tt, int zz, int yy) { return (((long)tt * L2 + zz) * L1 + yy) * hx; };
+  // sign of the +t and -t hops: forward (1 - gamma_t) for W, (1 + gamma_t) for W^dag
+  constexpr int SIG_TF = DAG ? -1 : +1;
+  constexpr int SIG_TB = DAG ? +1 : -1;
+  const int yp = y + 1 == L1 ? 0 : y + 1, ym = y == 0 ? L1 - 1 : y - 1;
+  const int zp = z + 1 == L2 ? 0 : z + 1, zm = z == 0 ? L2 - 1 : z - 1;
+  const int xslot = (sl + 1) * inner + lr;  // this lane's column in the exchange buffer
+
+  // column state: cur = input at (xh, t); hm = projected -t term for the output at t
+  cpx<R> cur[12];
+  cpx<R> hm[6];
+  if (valid) {
+    load_site_row<P>(a.in, a.in_sc, row(t0, z, y), xh, r, s, nrhs, NS, cur);
+    cpx<R> pv[12];
+    load_site_row<P>(a.in, a.in_sc, row(t0 == 0 ? L3 - 1 : t0 - 1, z, y), xh, r, s, nrhs, NS, pv);
+    if (t0 == 0 && a.bc_t < 0) {
+#pragma unroll
+      for (int c = 0; c < 12; c++) pv[c] = {-pv[c].re, -pv[c].im};
+    }
+    project<3, SIG_TB>(pv, hm);
+  }
+  double nval = 0.0;
+
+#pragma unroll 1
+  for (int t = t0; t < t0 + a.sweep; t++) {
+    const long rt = row(t, z, y);
+    const long j0 = rt + (long)seg * spb;
+    const long j = j0 + sl;
+    // the output site sits at x = 2 xh + shift: the own column is its +x
+    // neighbour when shift = 0 (the -x one is the previous lane's column), and
+    // its -x neighbour when shift = 1 (the +x one is the next lane's column)
+    const int shift = (y + z + t + a.out_par) & 1;
+    __syncthreads();  // readers of the previous step's links and buffers are done
+    stage_links<P>(a.links, j0, spb, lnk);
+    if (sl < spb) {
+#pragma unroll
+      for (int c = 0; c < 12; c++) buf[(size_t)c * xstride + xslot] = cur[c];
+      // halo: the column beyond the segment edge on the side this step needs
+      const bool edge = shift ? sl == spb - 1 : sl == 0;
+      if (edge && gate_on(a.gate, a.gate_mode, r)) {
+        const int xo = shift ? (xh + 1 == hx ? 0 : xh + 1) : (xh == 0 ? hx - 1 : xh - 1);
+        cpx<R> o[12];
+        load_site_row<P>(a.in, a.in_sc, rt, xo, r, s, nrhs, NS, o);
+        const int hs = xslot + (shift ? inner : -inner);
+#pragma unroll
+        for (int c = 0; c < 12; c++) buf[(size_t)c * xstride + hs] = o[c];
+      }
+    }
+    __syncthreads();
+
+    cpx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = {R(0), R(0)};
+    cpx<R> nxt[12];
+    if (valid) {
+      const cpx<R>* U = lnk + (size_t)sl * 8 * 9;
+      // terms summed in the order +x, -x, +y, -y, +z, -z, +t, -t, as in the
+      // one-t-per-block kernel, so that both round alike
+      {
+        cpx<R> o[12];
+        const int sp = xslot + (shift ? inner : 0), sm = xslot - (shift ? 0 : inner);
+#pragma unroll
+        for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + sp];
+        hop_one<0, DAG ? -1 : +1>(o, U + 0 * 9, acc);
+#pragma unroll
+        for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + sm];
+        hop_one<0, DAG ? +1 : -1>(o, U + 4 * 9, acc);
+      }
+      // y and z hops from the neighbouring columns, one direction pair per round
+#pragma unroll 1
+      for (int mu = 1; mu <= 2; mu++) {
+        cpx<R> pp[12], pm[12];
+        load_site_row<P>(a.in, a.in_sc, mu == 1 ? row(t, z, yp) : row(t, zp, y), xh, r, s, nrhs, NS, pp);
+        load_site_row<P>(a.in, a.in_sc, mu == 1 ? row(t, z, ym) : row(t, zm, y), xh, r, s, nrhs, NS, pm);
+        if (mu == 1) {
+          hop_one<1, DAG ? -1 : +1>(pp, U + 1 * 9, acc);
+          hop_one<1, DAG ? +1 : -1>(pm, U + 5 * 9, acc);
+        } else {
+          hop_one<2, DAG ? -1 : +1>(pp, U + 2 * 9, acc);
+          hop_one<2, DAG ? +1 : -1>(pm, U + 6 * 9, acc);
+        }
+      }
+      {  // +t: the next input of the own column
+        load_site_row<P>(a.in, a.in_sc, row(t + 1 == L3 ? 0 : t + 1, z, y), xh, r, s, nrhs, NS, nxt);
+        if (t + 1 == L3 && a.bc_t < 0) {
+#pragma unroll
+          for (int c = 0; c < 12; c++) nxt[c] = {-nxt[c].re, -nxt[c].im};
+        }
+        hop_one<3, SIG_TF>(nxt, U + 3 * 9, acc);
+      }
+      {  // -t: the projected input of the previous step
+        cpx<R> g[6];
+        su3_mul(U + 7 * 9, hm, g);
+        reconstruct<3, SIG_TB>(g, acc);
+      }
+#pragma unroll
+      for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
+      // the -t term of the next output is this step's own input
+      cpx<R> o[12];
+#pragma unroll
+      for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + xslot];
+      project<3, SIG_TB>(o, hm);
+    }
+
+    if constexpr (PLAIN) {
+      if (valid) store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+    } else {
+      __syncthreads();  // the x-exchange buffer becomes the column buffer
+      nval += fused_tail<P, NS>(a, acc, valid, j, sl, r, s, spb, buf, coef, kap, X_LOAD);
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 12; c++) cur[c] = nxt[c];
+    }
+  }
+
+  if (!PLAIN && a.partial) {
+    // one slot for the whole sweep, zeros in the slots of the other steps so
+    // that the partial array has the layout of the one-t-per-block kernel
+    red[tid] = valid ? nval : 0.0;
+    block_reduce_rhs(
+        red, blockDim.x, nrhs, [&](int k) { return (k % inner) / NS; }, rtmp, a.partial, blockIdx.x);
+    if (tid < nrhs) {
+      for (int k = 1; k < a.sweep; k++)
+        a.partial[((long)gridDim.x + (long)blockIdx.x * (a.sweep - 1) + (k - 1)) * nrhs + tid] = 0.0;
+    }
   }
 }
 
 template <class P, int NS>
-static size_t hop_smem(int spb, int nrhs, int block, bool plain) {
+static size_t hop_smem(int spb, int nrhs, int block, bool plain, bool sweep) {
   using R = typename P::real;
   const size_t lnk_n = (size_t)spb * 8 * 9;
-  const size_t buf_n = plain ? 0 : (size_t)spb * nrhs * 12 * (NS + 1);
+  const size_t col_n = plain ? 0 : (size_t)spb * nrhs * 12 * (NS + 1);
+  const size_t xch_n = (size_t)12 * (spb + 2) * nrhs * NS;  // x-exchange buffer with halo
+  const size_t buf_n = sweep ? (xch_n > col_n ? xch_n : col_n) : col_n;
   const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   size_t off = (region + MAXRHS * sizeof(R) + 15) & ~size_t(15);
   return off + (size_t)(block + 16 * MAXRHS) * sizeof(double);
@@ -465,10 +715,26 @@ static hipError_t launch_hop_t(HopArgs a, int dag, hipStream_t st) {
   if (inner > 256 || a.nrhs > MAXRHS) return hipErrorInvalidValue;
   a.spb = 256 / inner;
   const int block = (a.spb * inner + 63) & ~63;  // whole waves, <= 256
-  a.nblocks = (int)((a.h + a.spb - 1) / a.spb);
   const bool plain = a.prog_h.n == 0 && a.prog_o.n == 0 && a.xin == nullptr && a.partial == nullptr &&
                      a.c_h == 1.0;
-  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain);
+  const int hx = a.L[0] / 2;
+  const bool sweep = a.sweep > 0 && hx % a.spb == 0 && a.L[3] % a.sweep == 0 &&
+                     (a.tile_y <= 0 || a.L[1] % a.tile_y == 0) && (a.tile_z <= 0 || a.L[2] % a.tile_z == 0);
+  if (sweep) {
+    a.nblocks = (int)(a.h / a.spb / a.sweep);
+    const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain, true);
+    if (plain) {
+      if (dag) hipLaunchKernelGGL((hop_sweep_kernel<P, NS, true, true>), dim3(a.nblocks), dim3(block), sm, st, a);
+      else hipLaunchKernelGGL((hop_sweep_kernel<P, NS, false, true>), dim3(a.nblocks), dim3(block), sm, st, a);
+    } else {
+      if (dag) hipLaunchKernelGGL((hop_sweep_kernel<P, NS, true, false>), dim3(a.nblocks), dim3(block), sm, st, a);
+      else hipLaunchKernelGGL((hop_sweep_kernel<P, NS, false, false>), dim3(a.nblocks), dim3(block), sm, st, a);
+    }
+    return hipGetLastError();
+  }
+  a.sweep = 0;
+  a.nblocks = (int)((a.h + a.spb - 1) / a.spb);
+  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain, false);
   if (plain) {
     if (dag) hipLaunchKernelGGL((hop_kernel<P, NS, true, true>), dim3(a.nblocks), dim3(block), sm, st, a);
     else hipLaunchKernelGGL((hop_kernel<P, NS, false, true>), dim3(a.nblocks), dim3(block), sm, st, a);

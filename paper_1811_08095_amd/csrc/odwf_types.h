@@ -101,8 +101,14 @@ struct HopArgs {
   int nblocks;
   // block traversal: xcd != 0 gives each of the 8 XCDs a contiguous range of
   // logical blocks; tile_y, tile_z > 0 walk (x-row segment, y, z) tiles with t
-  // innermost so that t-neighbours are re-read while still in L2
-  int xcd, tile_y, tile_z;
+  // innermost so that t-neighbours are re-read while still in L2; tile_t > 0
+  // cuts t into chunks of that length, each chunk walking all (y, z) tiles
+  // before the next chunk starts, so that a tile's y/z halo rows are re-read
+  // by the adjacent tile soon after they were fetched
+  int xcd, tile_y, tile_z, tile_t;
+  // t-sweep kernel: > 0 is the number of consecutive t each block walks for
+  // its (x-row segment, y, z) column; 0 selects the one-t-per-block kernel
+  int sweep;
   // gating: lanes of right-hand sides not selected by gate_mode do no work
   const CGScal* gate;
   int gate_mode;

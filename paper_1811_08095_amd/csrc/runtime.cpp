@@ -110,14 +110,14 @@ static size_t site_bytes(int prec) {
 // ---- block traversal of the hopping kernel -------------------------------------
 // Defaults: XCD-aware contiguous block ranges, and a t-innermost walk over
 // (y, z) tiles when the x-rows split evenly into blocks.  ODWF_TRAVERSAL
-// ("linear", "xcd", or "Ty,Tz") overrides for tuning.
+// ("linear", "xcd", "Ty,Tz" or "Ty,Tz,Tt") overrides for tuning.
 static void traversal(HopArgs& a, int Ns) {
   const int inner = a.nrhs * Ns;
   const int spb = 256 / inner;
   const int hx = a.L[0] / 2;
   a.xcd = 1;
-  a.tile_y = a.tile_z = 0;
-  int ty = 4, tz = 4;
+  a.tile_y = a.tile_z = a.tile_t = 0;
+  int ty = 4, tz = 4, tt = 0;
   const char* env = getenv("ODWF_TRAVERSAL");
   if (env) {
     if (!strcmp(env, "linear")) {
@@ -125,11 +125,20 @@ static void traversal(HopArgs& a, int Ns) {
       return;
     }
     if (!strcmp(env, "xcd")) return;
-    if (sscanf(env, "%d,%d", &ty, &tz) != 2) return;
+    const int n = sscanf(env, "%d,%d,%d", &ty, &tz, &tt);
+    if (n < 2) return;
+    if (n < 3) tt = 0;
   }
   if (ty > 0 && tz > 0 && hx % spb == 0 && a.L[1] % ty == 0 && a.L[2] % tz == 0) {
     a.tile_y = ty;
     a.tile_z = tz;
+    if (tt > 0 && a.L[3] % tt == 0) a.tile_t = tt;
+  }
+  // t-sweep kernel: blocks walk sweep consecutive t of one column
+  a.sweep = 0;
+  if (const char* sw = getenv("ODWF_SWEEP")) {
+    const int n = atoi(sw);
+    if (n > 0 && hx % spb == 0 && a.L[3] % n == 0) a.sweep = n;
   }
 }
 
