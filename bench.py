@@ -69,6 +69,26 @@ def cpu_baseline(sample_dims, Ns, target_s=12.0):
                       f"same algorithmic byte count as the GPU FP64 hop"}
 
 
+def serving_leg(nreq, rate, inner="fp32"):
+    """Serving stream: Poisson arrivals over resident 8^4, 16^4 and 24^4 (Ns = 16,
+    eps = 0.5) gauge fields, m_q from {0.005, 0.04, 0.5}, 1-12 right-hand sides
+    and tolerance 1e-8 or 1e-10 per request, continuous batching into 12-slot
+    multi-RHS engines; latency = completion - arrival (queueing included)."""
+    from paper_1811_08095_amd import serve
+    lattices = {f"{L}^4": {"dims": (L, L, L, L), "Ns": 16, "eps": 0.5, "seed": 0} for L in (8, 16, 24)}
+    srv = serve.Server(lattices, max_slots=12, inner=inner)
+    reqs = serve.poisson_stream(nreq, rate, list(lattices))
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    out = serve.summarize(done, time.perf_counter() - t0)
+    out.update({"arrival_rate": rate, "lattices": list(lattices), "max_slots": 12, "inner": inner})
+    for e in srv.engines.values():
+        e["batch"].close()
+        e["sol"].close()
+        e["lat"].close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +104,9 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 CG comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="16,16,16,16")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rate", type=float, default=0.5, help="Poisson arrivals per second")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (the reference dispatch "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters under rocprofv3)")
@@ -218,6 +241,14 @@ def main():
                                   "true_rel_resid": st64[0]["true_rel_resid"],
                                   "speedup_mixed_over_fp64": round(t64 / (sum(t_mixed) / len(t_mixed)), 3)
                                   if t_mixed else None}
+    if not args.no_serving:
+        # release the 64^4 fields first: the serving leg has its own resident lattices
+        sol.close()
+        lat.close()
+        del b, x
+        torch.cuda.empty_cache()
+        result["serving"] = serving_leg(args.serve_requests, args.serve_rate,
+                                        inner=args.inner if args.inner in ("fp32", "fp64") else "fp32")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(parse_dims(args.cpu_sample), Ns)
     print(json.dumps(result), flush=True)

@@ -9,7 +9,10 @@ stream; gauge fields and solver state stay resident.  The loop
   2. admits queued requests while their engine has enough free slots and the
      in-flight HBM footprint stays within the budget,
   3. enqueues a few CG iterations on every engine that has work (the engines'
-     streams overlap on the device),
+     streams overlap on the device); an engine over a smaller lattice takes
+     proportionally more iterations per step (up to 16x), so that every step
+     is a similar slice of device time and the host's per-step polling does
+     not dominate small lattices,
   4. polls the slots, retires finished requests and records their latency
      (completion - arrival, queueing included).
 
@@ -100,7 +103,7 @@ class Server:
     """Resident lattices with one batch engine each."""
 
     def __init__(self, lattices: Dict[str, dict], max_slots=12, inner="fp32", hbm_budget=None,
-                 iters_per_step=4, m0=1.3, lmin=0.05, lmax=6.2):
+                 iters_per_step=4, m0=1.3, lmin=0.05, lmax=6.2, scale_steps=True):
         import torch
 
         from . import odwf, synth
@@ -122,6 +125,12 @@ class Server:
             self.engines[name] = {"lat": lat, "sol": sol, "batch": bt, "stream": stream,
                                   "dims": dims, "Ns": Ns, "active": []}
             per_slot[name] = odwf.footprint(dims, Ns, 1, inner_p)
+        # iterations per step: iters_per_step on the largest lattice, more on smaller ones
+        vmax = max(int(np.prod(e["dims"])) * e["Ns"] for e in self.engines.values())
+        for e in self.engines.values():
+            v = int(np.prod(e["dims"])) * e["Ns"]
+            mult = min(16, max(1, vmax // v)) if scale_steps else 1
+            e["iters"] = self.iters_per_step * mult
         torch.cuda.synchronize()
         budget = hbm_budget if hbm_budget is not None else float("inf")
         self.admission = Admission({n: max_slots for n in lattices}, per_slot, budget)
@@ -164,7 +173,7 @@ class Server:
                     time.sleep(min(0.002, max(0.0, pending[pi].arrival - now)))
                 continue
             for e in busy:
-                e["batch"].step(self.iters_per_step, stream=e["stream"])
+                e["batch"].step(e["iters"], stream=e["stream"])
             for e in busy:
                 still = []
                 for req in e["active"]:
