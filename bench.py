@@ -69,6 +69,34 @@ def cpu_baseline(sample_dims, Ns, target_s=12.0):
                       f"same algorithmic byte count as the GPU FP64 hop"}
 
 
+def hop_micro(lat, Ns, omega, b, o, mq, stream, warm=3, reps=20):
+    """Plain even-odd hop W_eo on the bench lattice, per storage precision:
+    3 warm-up launches, then 20 timed launches (HIP events of the library),
+    median / min / max launch time and GB/s with the algorithmic byte count.
+    `o` is an output buffer of the source's shape (overwritten)."""
+    import numpy as np
+    from paper_1811_08095_amd import odwf
+    out = {}
+    sol = odwf.Solver(lat, Ns, 1.3, omega)
+    for name, prec in (("fp64", odwf.FP64), ("fp32", odwf.FP32), ("fp16s", odwf.FP16S)):
+        for _ in range(warm):
+            sol.apply(odwf.OP_HOP_EO, b, [mq], prec=prec, out=o, stream=stream)
+        ts, gb = [], 0.0
+        for _ in range(reps):
+            odwf.profile_enable(True)
+            sol.apply(odwf.OP_HOP_EO, b, [mq], prec=prec, out=o, stream=stream)
+            n, ms, by = odwf.profile_read()
+            odwf.profile_enable(False)
+            ts.append(ms / max(n, 1))
+            gb = by / max(n, 1) / 1e9
+        ts = np.array(ts)
+        out[name] = {"median_ms": round(float(np.median(ts)), 4), "min_ms": round(float(ts.min()), 4),
+                     "max_ms": round(float(ts.max()), 4), "gb_per_launch": round(gb, 3),
+                     "gbs_median": round(gb / (float(np.median(ts)) * 1e-3), 1)}
+    sol.close()
+    return out
+
+
 def serving_leg(nreq, rate, inner="fp32"):
     """Serving stream: Poisson arrivals over resident 8^4, 16^4 and 24^4 (Ns = 16,
     eps = 0.5) gauge fields, m_q from {0.005, 0.04, 0.5}, 1-12 right-hand sides
@@ -105,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="16,16,16,16")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--no-hop-micro", action="store_true", help="skip the plain-hop microbenchmark")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rate", type=float, default=0.5, help="Poisson arrivals per second")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -231,25 +260,42 @@ def main():
         sol.close()
         torch.cuda.synchronize()
         sol = odwf.Solver(lat, Ns, 1.3, omega)
+        print("# plain FP64 CG comparison ...", file=sys.stderr, flush=True)
+        odwf.profile_enable(True)
         t1 = time.perf_counter()
         _, st64 = sol.solve(b, [masses[0]], [args.tol], inner=odwf.FP64, maxiter=args.maxiter, x=x,
                             stream=stream)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
+        n64, ms64, by64 = odwf.profile_read()
+        odwf.profile_enable(False)
+        print(f"# FP64 CG: {st64[0]['iters']} iterations, {t64:.1f} s", file=sys.stderr, flush=True)
         t_mixed = [s["seconds"] for s in stats_all if s["mq"] == masses[0]]
         result["fp64_compare"] = {"mq": masses[0], "seconds": round(t64, 3), "iters": st64[0]["iters"],
                                   "true_rel_resid": st64[0]["true_rel_resid"],
                                   "speedup_mixed_over_fp64": round(t64 / (sum(t_mixed) / len(t_mixed)), 3)
-                                  if t_mixed else None}
+                                  if t_mixed else None,
+                                  "dslash_gbs_fp64": round(by64 / (ms64 * 1e-3) / 1e9, 1) if ms64 > 0 else None,
+                                  "dslash_launches": n64}
+    if not args.no_hop_micro:
+        sol.close()  # the solve workspaces are not needed by the plain hop
+        torch.cuda.empty_cache()
+        print("# plain-hop microbenchmark ...", file=sys.stderr, flush=True)
+        result["hop_micro"] = hop_micro(lat, Ns, omega, b, x, masses[0], stream)
+        print(f"# hop: {json.dumps(result['hop_micro'])}", file=sys.stderr, flush=True)
     if not args.no_serving:
         # release the 64^4 fields first: the serving leg has its own resident lattices
         sol.close()
         lat.close()
         del b, x
         torch.cuda.empty_cache()
+        print(f"# serving stream: {args.serve_requests} requests at {args.serve_rate}/s ...",
+              file=sys.stderr, flush=True)
         result["serving"] = serving_leg(args.serve_requests, args.serve_rate,
                                         inner=args.inner if args.inner in ("fp32", "fp64") else "fp32")
+        print(f"# serving: {json.dumps(result['serving'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
+        print("# CPU oracle baseline ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(parse_dims(args.cpu_sample), Ns)
     print(json.dumps(result), flush=True)
 
