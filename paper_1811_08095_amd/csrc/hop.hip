@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const
 // the one-t-per-block kernel.
 // ---------------------------------------------------------------------------
 #ifndef ODWF_SWEEP_WAVES_PLAIN
-#define ODWF_SWEEP_WAVES_PLAIN 4
+#define ODWF_SWEEP_WAVES_PLAIN 2
 #endif
 // minimum waves per SIMD of the t-sweep kernel (its column state costs registers)
 template <class P, bool PLAIN>
