@@ -62,7 +62,7 @@ def cpu_baseline(sample_dims, Ns, target_s=12.0):
         oracle.apply(oracle.OP_HOP_EO, U, psi, 1.3, w, 0.0)
     dt = (time.perf_counter() - t0) / reps
     by = hop_bytes_plain(sample_dims, Ns, 8, 144)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.num_threads()
     return {"value": by / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle even-odd hop W_eo on {'x'.join(map(str, sample_dims))} x Ns={Ns}, "
                       f"{reps} reps of {dt:.3f} s (whole job {one + reps * dt:.1f} s), "

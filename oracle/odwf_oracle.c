@@ -45,6 +45,9 @@
  * Parity of a site is (x + y + z + t) mod 2; 0 = even.
  */
 #include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -529,6 +532,15 @@ static int apply_op(const ctx_t* c, int op, const cplx* in, cplx* out) {
 /* ------------------------------------------------------------------------ */
 /* exported entry points                                                    */
 /* ------------------------------------------------------------------------ */
+
+/* number of threads the oracle's parallel loops use */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* gamma matrices as the oracle builds them: out[5][4][4] (gamma_1..4, gamma5) */
 void oracle_gammas(cplx* out) {

@@ -47,6 +47,7 @@ def lib():
                                              ctypes.c_double, _f64p, ctypes.c_double,
                                              _c128p, _c128p]
         L.oracle_normal_residual.restype = ctypes.c_double
+        L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -54,6 +55,11 @@ def lib():
 def _dims(U):
     T, Z, Y, X = U.shape[:4]
     return np.array([X, Y, Z, T], dtype=np.int32)
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().oracle_num_threads())
 
 
 def gammas():
