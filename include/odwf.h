@@ -41,6 +41,14 @@
  *     one solver from several threads are serialised by a lock; the solver
  *     keeps its workspaces per stream, so calls on different streams never
  *     share a buffer.  A batch is used from one thread at a time.
+ *   - Tuning (environment, read at every hopping-kernel launch; results do not
+ *     depend on them beyond rounding order of the partial sums):
+ *       ODWF_TRAVERSAL = "linear" | "xcd" | "Ty,Tz" | "Ty,Tz,Tt"  block order of
+ *         the hopping kernel (default "4,4": XCD-aware ranges, (y, z) tiles of
+ *         4 x 4 walked with t innermost; Tt > 0 cuts t into chunks of Tt);
+ *       ODWF_SWEEP = n  blocks walk n consecutive t of one x-row segment and
+ *         carry the own column in registers (used when Lx/2 is a multiple of
+ *         256 / (nrhs Ns) sites and n divides Lt; default off).
  */
 #ifndef ODWF_H
 #define ODWF_H
