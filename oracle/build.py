@@ -12,14 +12,18 @@ SRC = os.path.join(HERE, "odwf_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, plant: int = 0) -> str:
+    """Compile the oracle; plant = k > 0 builds the mutation-test variant with
+    planted mistake k (tests only, written to `out`)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-           "-Wno-unused-function", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-Wno-unused-function", SRC, "-o", out + ".tmp", "-lm"]
+    if plant:
+        cmd.insert(1, f"-DORACLE_PLANT={int(plant)}")
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def ensure_built() -> str:

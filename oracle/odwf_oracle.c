@@ -37,6 +37,10 @@
  *   - §2 (conjugate gradient): the solve is textbook Hestenes-Stiefel CG on
  *     the Hermitian positive-definite normal operator S_e^dag S_e.
  *
+ * Mutation testing: building with -DORACLE_PLANT=k (k = 1..9) plants one
+ * deliberate, plausible mistake (see PLANT below) so that the tests can show
+ * that their pins reject it; the normal build never defines it.
+ *
  * Conventions: gamma matrices in the chiral basis
  *     gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = 1, 2, 3),
  *     gamma_4 = [[0, 1], [1, 0]],   gamma5 = gamma1 gamma2 gamma3 gamma4.
@@ -53,6 +57,11 @@
 #include <string.h>
 
 typedef double complex cplx;
+
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
+#define PLANT(k) (ORACLE_PLANT == (k))
 
 enum {
   OR_OP_HOP_EO = 0,
@@ -147,7 +156,7 @@ static int site_parity(const geom_t* g, long i) {
 static long neighbour(const geom_t* g, long i, int mu, int step, double* sign) {
   int c[4];
   site_coords(g, i, c);
-  int v = c[mu] + step;
+  int v = c[mu] + (PLANT(9) && mu == 2 ? -step : step);
   *sign = 1.0;
   if (v >= g->L[mu]) {
     v -= g->L[mu];
@@ -176,6 +185,7 @@ static void wilson_hop_4d(const geom_t* g, const cplx* U, int dag, const cplx* i
                           cplx* out, int out_par, int in_par) {
   init_gamma();
   double fwd_sign = dag ? +1.0 : -1.0; /* sign of gamma_mu on the forward hop */
+  if (PLANT(1)) fwd_sign = -fwd_sign;
 #pragma omp parallel for schedule(static)
   for (long x = 0; x < g->V; x++) {
     cplx acc[4][3];
@@ -199,7 +209,7 @@ static void wilson_hop_4d(const geom_t* g, const cplx* U, int dag, const cplx* i
         } else {
           const cplx* u = U + (y * 4 + mu) * 9;
           for (int a = 0; a < 3; a++)
-            for (int b = 0; b < 3; b++) link[a][b] = conj(u[b * 3 + a]);
+            for (int b = 0; b < 3; b++) link[a][b] = PLANT(2) ? u[a * 3 + b] : conj(u[b * 3 + a]);
         }
         /* projector (1 + s gamma_mu): forward s = fwd_sign, backward -fwd_sign */
         double s = dir == 0 ? fwd_sign : -fwd_sign;
@@ -219,7 +229,7 @@ static void wilson_hop_4d(const geom_t* g, const cplx* U, int dag, const cplx* i
           for (int a = 0; a < 3; a++) {
             cplx v = 0;
             for (int t = 0; t < 4; t++) v += proj[sp][t] * up[t][a];
-            acc[sp][a] += -0.5 * bsign * v;
+            acc[sp][a] += (PLANT(8) ? -1.0 : -0.5) * (PLANT(3) ? 1.0 : bsign) * v;
           }
       }
     }
@@ -294,15 +304,16 @@ static int m5_matrix(int Ns, double m0, const double* omega, double mu, int whic
   double* Lp = calloc((size_t)Ns * Ns, sizeof(double));
   double* Lm = calloc((size_t)Ns * Ns, sizeof(double));
   for (int s = 1; s < Ns; s++) Lp[s * Ns + s - 1] = 1.0;
-  Lp[0 * Ns + Ns - 1] = -mu;
+  Lp[0 * Ns + Ns - 1] = PLANT(4) ? mu : -mu;
   for (int s = 0; s < Ns - 1; s++) Lm[s * Ns + s + 1] = 1.0;
-  Lm[(Ns - 1) * Ns + 0] = -mu;
+  Lm[(Ns - 1) * Ns + 0] = PLANT(4) ? mu : -mu;
   cplx* L = calloc((size_t)n * n, sizeof(cplx));
   for (int s = 0; s < Ns; s++)
     for (int t = 0; t < Ns; t++)
       for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++)
-          L[(s * 4 + a) * n + t * 4 + b] = Lm[s * Ns + t] * Pm[a][b] + Lp[s * Ns + t] * Pp[a][b];
+          L[(s * 4 + a) * n + t * 4 + b] = PLANT(5) ? Lm[s * Ns + t] * Pm[a][b] + Lm[s * Ns + t] * Pp[a][b]
+                                                    : Lm[s * Ns + t] * Pm[a][b] + Lp[s * Ns + t] * Pp[a][b];
   int rc = 0;
   cplx* one_plus = calloc((size_t)n * n, sizeof(cplx));
   cplx* one_minus = calloc((size_t)n * n, sizeof(cplx));
@@ -442,7 +453,7 @@ static void op_D(const ctx_t* c, const cplx* in, cplx* out) {
   long vs = c->g.V * 12;
   for (long i = 0; i < n; i++) {
     double w = c->omega[i / vs];
-    out[i] = w * (dw[i] + (4.0 - c->m0) * y[i]) + in[i] - Lpsi[i];
+    out[i] = w * (dw[i] + ((PLANT(6) ? 5.0 : 4.0) - c->m0) * y[i]) + in[i] - Lpsi[i];
   }
   free(Lpsi); free(y); free(dw);
 }
@@ -479,7 +490,7 @@ static void op_schur(const ctx_t* c, const cplx* in, cplx* out) {
   cplx* e = malloc(sizeof(cplx) * n);
   memcpy(e, in, sizeof(cplx) * n);
   mask_parity(&c->g, c->Ns, e, 1);
-  for (long i = 0; i < n; i++) out[i] = e[i] - t2[i];
+  for (long i = 0; i < n; i++) out[i] = PLANT(7) ? e[i] + t2[i] : e[i] - t2[i];
   free(t1); free(t2); free(e);
 }
 

@@ -8,6 +8,7 @@ All fields are numpy complex128 arrays in the canonical layouts:
   gauge   U[t][z][y][x][mu][3][3]
   spinor  psi[s][t][z][y][x][spin][color]   (one right-hand side)
 """
+import contextlib
 import ctypes
 import os
 
@@ -29,27 +30,43 @@ _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 def lib():
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
-        L = ctypes.CDLL(path)
-        L.oracle_gammas.argtypes = [_c128p]
-        L.oracle_dw.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_double, ctypes.c_int,
-                                _c128p, _c128p]
-        L.oracle_m5_matrix.argtypes = [ctypes.c_int, ctypes.c_double, _f64p, ctypes.c_double,
-                                       ctypes.c_int, _c128p]
-        L.oracle_apply.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_double,
-                                   _f64p, ctypes.c_double, ctypes.c_int, _c128p, _c128p]
-        L.oracle_solve.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_double,
-                                   _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                   ctypes.c_int, _c128p, _c128p,
-                                   ctypes.POINTER(ctypes.c_double),
-                                   ctypes.POINTER(ctypes.c_double)]
-        L.oracle_normal_residual.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int,
-                                             ctypes.c_double, _f64p, ctypes.c_double,
-                                             _c128p, _c128p]
-        L.oracle_normal_residual.restype = ctypes.c_double
-        L.oracle_num_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = _open(_build.ensure_built())
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path):
+    """Run the oracle from another build of it (the mutation tests' variants
+    with a planted mistake) inside the with-block."""
+    global _lib
+    saved = _lib
+    _lib = _open(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _open(path):
+    L = ctypes.CDLL(path)
+    L.oracle_gammas.argtypes = [_c128p]
+    L.oracle_dw.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_double, ctypes.c_int,
+                            _c128p, _c128p]
+    L.oracle_m5_matrix.argtypes = [ctypes.c_int, ctypes.c_double, _f64p, ctypes.c_double,
+                                   ctypes.c_int, _c128p]
+    L.oracle_apply.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_double,
+                               _f64p, ctypes.c_double, ctypes.c_int, _c128p, _c128p]
+    L.oracle_solve.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_double,
+                               _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_int, _c128p, _c128p,
+                               ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)]
+    L.oracle_normal_residual.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int,
+                                         ctypes.c_double, _f64p, ctypes.c_double,
+                                         _c128p, _c128p]
+    L.oracle_normal_residual.restype = ctypes.c_double
+    L.oracle_num_threads.restype = ctypes.c_int
+    return L
 
 
 def _dims(U):
