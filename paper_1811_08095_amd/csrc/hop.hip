@@ -341,7 +341,7 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
 // minimum waves per SIMD the register allocation must allow
 template <class P, bool PLAIN>
 struct HopWaves {
-  static constexpr int W = sizeof(typename P::real) == 8 ? (PLAIN ? 2 : 1) : (PLAIN ? 4 : 2);
+  static constexpr int W = sizeof(typename P::real) == 8 ? 2 : (PLAIN ? 4 : 2);
 };
 
 template <class P, int NS, bool DAG, bool PLAIN>
