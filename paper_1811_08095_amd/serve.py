@@ -149,8 +149,9 @@ class Server:
         req.admitted = now
         e["active"].append(req)
 
-    def run(self, requests: List[Request], time_limit=600.0, keep_solutions=False):
-        """Serve the stream in real time; returns the finished requests."""
+    def run(self, requests: List[Request], time_limit=600.0, keep_solutions=False, progress=None):
+        """Serve the stream in real time; returns the finished requests.  With
+        `progress` (a text stream) one line is written per finished request."""
         torch = self.torch
         queues = collections.defaultdict(collections.deque)
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -194,6 +195,10 @@ class Server:
                     self.admission.release(req)
                     req.b = None
                     done.append(req)
+                    if progress is not None:
+                        print(f"# {len(done)}/{len(requests)} {req.lattice} m_q={req.mq} "
+                              f"nrhs={req.nrhs} tol={req.tol:g} latency {req.latency:.3f} s",
+                              file=progress, flush=True)
                 e["active"] = still
         return done
 
@@ -211,31 +216,40 @@ def summarize(done: List[Request], makespan: float):
 
 def main():
     import argparse
+    import sys
     ap = argparse.ArgumentParser(description="serve a Poisson stream of ODWF solve requests")
     ap.add_argument("--requests", type=int, default=60)
-    ap.add_argument("--rate", type=float, default=0.0, help="arrivals/s (0: measure saturation)")
-    ap.add_argument("--load", type=float, default=0.8, help="fraction of saturation throughput")
+    ap.add_argument("--rate", type=float, default=0.0, help="arrivals/s (0: a fraction of saturation)")
+    ap.add_argument("--loads", default="0.8",
+                    help="comma list of fractions of the measured saturation throughput")
     ap.add_argument("--sizes", default="8,16,24")
     ap.add_argument("--Ns", type=int, default=16)
     ap.add_argument("--max-slots", type=int, default=12)
     ap.add_argument("--inner", default="fp32")
+    ap.add_argument("--time-limit", type=float, default=900.0)
+    ap.add_argument("--progress", action="store_true", help="one line per finished request on stderr")
     args = ap.parse_args()
     lattices = {f"{L}^4": {"dims": (L, L, L, L), "Ns": args.Ns, "eps": 0.5, "seed": 0}
                 for L in (int(v) for v in args.sizes.split(","))}
     srv = Server(lattices, max_slots=args.max_slots, inner=args.inner)
-    rate = args.rate
-    if rate <= 0:  # saturation: everything arrives at once
+    prog = sys.stderr if args.progress else None
+    rates = [(None, args.rate)]
+    sat = None
+    if args.rate <= 0:  # saturation: a warm-up stream that arrives all at once
         warm = poisson_stream(min(24, args.requests), 1e9, list(lattices), seed=3)
         t = time.perf_counter()
-        d = srv.run(warm)
+        d = srv.run(warm, time_limit=args.time_limit, progress=prog)
         sat = len(d) / (time.perf_counter() - t)
-        rate = args.load * sat
-    reqs = poisson_stream(args.requests, rate, list(lattices))
-    t = time.perf_counter()
-    done = srv.run(reqs)
-    out = summarize(done, time.perf_counter() - t)
-    out["arrival_rate"] = round(rate, 3)
-    print(json.dumps(out))
+        rates = [(float(f), float(f) * sat) for f in args.loads.split(",")]
+    for load, rate in rates:
+        reqs = poisson_stream(args.requests, rate, list(lattices))
+        t = time.perf_counter()
+        done = srv.run(reqs, time_limit=args.time_limit, progress=prog)
+        out = summarize(done, time.perf_counter() - t)
+        out.update({"arrival_rate": round(rate, 4), "load": load,
+                    "saturation_requests_per_s": round(sat, 4) if sat else None,
+                    "submitted": len(reqs)})
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
