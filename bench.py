@@ -13,9 +13,12 @@ The JSON line reports the Dslash (hopping-kernel) HBM bandwidth measured live
 with HIP events recorded by the library around every hopping-kernel launch on
 its stream, over the timed steps: algorithmic bytes (spinor reads and writes
 plus link reads per launch) divided by summed kernel time, against the 8 TB/s
-HBM peak.  Beside it: solves/s, iterations per mass, device memory footprint,
-optionally the plain FP64 CG on the same GPU, and the FP64 CPU oracle's hopping
-term timed on the host cores over a bounded sample lattice.
+HBM peak, with the copy-calibrated L2-to-fabric traffic per launch when a
+counter summary of the same kernel sources is committed.  Beside it: solves/s,
+iterations per mass, device memory footprint, the plain FP64 CG on the same
+GPU, a plain-hop microbenchmark per precision, a short serving stream (p50/p99
+latency), and the FP64 CPU oracle timed on the host cores (its hopping term on
+a bounded sample lattice, and the small FP64 solve beside the GPU's).
 """
 import argparse
 import json
@@ -67,6 +70,37 @@ def cpu_baseline(sample_dims, Ns, target_s=12.0):
             "sample": f"FP64 oracle even-odd hop W_eo on {'x'.join(map(str, sample_dims))} x Ns={Ns}, "
                       f"{reps} reps of {dt:.3f} s (whole job {one + reps * dt:.1f} s), "
                       f"same algorithmic byte count as the GPU FP64 hop"}
+
+
+def small_solve_comparison():
+    """The plain FP64 configuration (4^4 lattice, Ns = 8, eps = 0.3 links from
+    seed 0, m_q = 0.05, one Gaussian source from seed 1000, tol 1e-10): the FP64
+    oracle's even-odd CG FULL solve on the host cores beside the GPU's FP64 solve
+    of the same system (after one warm-up solve)."""
+    import torch
+    from oracle import oracle
+    from paper_1811_08095_amd import odwf, synth
+    dims, Ns, mq = (4, 4, 4, 4), 8, 0.05
+    U = synth.make_gauge(dims, 0.3, 0)
+    b = synth.make_source(dims, Ns, 1, 1000)
+    w = odwf.zolotarev_omega(Ns, 0.05, 6.2)
+    t0 = time.perf_counter()
+    _, it, _, _ = oracle.solve(U, b[0], 1.3, w, mq / 2.6, oracle.SOLVE_FULL, tol=1e-10)
+    cpu_s = time.perf_counter() - t0
+    lat = odwf.Lattice(dims, bc_t=-1)
+    lat.load_gauge(U)
+    sol = odwf.Solver(lat, Ns, 1.3, w)
+    bd = torch.from_numpy(b).cuda()
+    sol.solve(bd, [mq], [1e-10], inner=odwf.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sol.solve(bd, [mq], [1e-10], inner=odwf.FP64)
+    gpu_s = time.perf_counter() - t0
+    sol.close()
+    lat.close()
+    return {"config": "4x4x4x4, Ns=8, eps=0.3, m_q=0.05, tol 1e-10, FP64 even-odd CG (FULL)",
+            "cpu_oracle_s": round(cpu_s, 4), "cpu_oracle_iters": it,
+            "gpu_s": round(gpu_s, 4), "gpu_iters": st[0]["iters"]}
 
 
 def hop_micro(lat, Ns, omega, b, o, mq, stream, warm=3, reps=20):
@@ -297,6 +331,7 @@ def main():
     if not args.no_cpu_baseline:
         print("# CPU oracle baseline ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(parse_dims(args.cpu_sample), Ns)
+        result["cpu_baseline"]["solve_small"] = small_solve_comparison()
     print(json.dumps(result), flush=True)
 
 
