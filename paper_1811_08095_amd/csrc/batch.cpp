@@ -200,7 +200,7 @@ extern "C" odwf_status odwf_batch_admit(odwf_batch B, const void* b, double mq, 
   c.tol2 = tol * tol;
   c.maxiter = maxiter;
   c.confirm = 1;
-  c.delta2 = B->inner == PREC64 ? 0.0 : 1e-2;
+  c.delta2 = B->inner == PREC64 ? 0.0 : RELIABLE_DELTA2;
   if (!std::isfinite(f2)) {
     c.nan = 1;
   } else if (f2 == 0.0) {

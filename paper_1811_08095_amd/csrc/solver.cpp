@@ -253,7 +253,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     hs[r].tol2 = tol[r] * tol[r];
     hs[r].maxiter = maxiter;
     hs[r].active = 1;
-    hs[r].delta2 = inner == PREC32 ? 1e-2 : 0.0;
+    hs[r].delta2 = inner == PREC32 ? RELIABLE_DELTA2 : 0.0;
     hs[MAXRHS + r] = hs[r];
     hs[MAXRHS + r].delta2 = 0.0;
   }
