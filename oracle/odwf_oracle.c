@@ -465,7 +465,7 @@ static void op_Ddag(const ctx_t* c, const cplx* in, cplx* out) {
   long vs = c->g.V * 12;
   cplx* Ldag = malloc(sizeof(cplx) * m * m);
   cadjoint(m, c->L, Ldag);
-  cplx* w = malloc(sizeof(cplx) * n);
+  cplx* w = calloc((size_t)n, sizeof(cplx)); /* every entry is set below */
   cplx* dw = malloc(sizeof(cplx) * n);
   cplx* t1 = malloc(sizeof(cplx) * n);
   cplx* t2 = malloc(sizeof(cplx) * n);
