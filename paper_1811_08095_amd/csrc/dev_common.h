@@ -226,6 +226,26 @@ __device__ __forceinline__ void load_site_row(const void* base, const float* sca
   }
 }
 
+// cached neighbour read without the per-site scale applied: v holds the
+// stored values, *sc the site's scale (1 for unscaled formats), so that the
+// caller can apply the scale after its linear algebra on fewer numbers
+template <class P>
+__device__ __forceinline__ void load_site_cached_raw(const void* base, const float* scale, long j,
+                                                     int r, int s, int nrhs, int Ns,
+                                                     cpx<typename P::real> (&v)[12],
+                                                     typename P::real& sc) {
+  constexpr int NCG = 12 / P::CPB;
+  const uint4* b = reinterpret_cast<const uint4*>(base);
+  const long off = ((j * nrhs + r) * NCG) * Ns + s;
+  uint4 q[NCG];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
+#pragma unroll
+  for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
+  if constexpr (P::SCALED) sc = scale[(j * nrhs + r) * Ns + s];
+  else sc = typename P::real(1);
+}
+
 template <class P>
 __device__ __forceinline__ void store_site(void* base, float* scale, long j, int r, int s, int nrhs,
                                            int Ns, const cpx<typename P::real> (&v)[12]) {

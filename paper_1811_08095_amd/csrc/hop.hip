@@ -186,6 +186,20 @@ __device__ __forceinline__ void hop_one(const cpx<R> (&psi)[12], const cpx<R>* U
   reconstruct<MU, SIG>(g, acc);
 }
 
+// the same hop for a neighbour stored with a per-site scale: the projection and
+// the link product are linear, so the scale multiplies the 6 numbers of g
+// instead of the 12 of the spinor
+template <int MU, int SIG, class R>
+__device__ __forceinline__ void hop_one_scaled(const cpx<R> (&psi)[12], R sc, const cpx<R>* U,
+                                               cpx<R> (&acc)[12]) {
+  cpx<R> h[6], g[6];
+  project<MU, SIG>(psi, h);
+  su3_mul(U, h, g);
+#pragma unroll
+  for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
+  reconstruct<MU, SIG>(g, acc);
+}
+
 // first site of this block under the configured traversal
 __device__ __forceinline__ long block_first_site(const HopArgs& a) {
   int lb = blockIdx.x;
@@ -430,6 +444,7 @@ __global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const
 #pragma unroll 1
     for (int g0 = 0; g0 < 8; g0 += G) {
       cpx<R> psi[G][12];
+      R scl[G];  // per-site scales of the neighbours (scaled formats)
 #pragma unroll
       for (int k = 0; k < G; k++) {
         const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);  // 0,4,1,5,2,6,3,7
@@ -441,23 +456,38 @@ __global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const
         if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
         if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
         const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
-        load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
+        if constexpr (P::SCALED) load_site_cached_raw<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k], scl[k]);
+        else load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
       }
 #pragma unroll
       for (int k = 0; k < G; k++) {
         const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);
         const bool fwd = dir < 4;
         if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
+          if constexpr (P::SCALED) {
+            scl[k] = -scl[k];
+          } else {
 #pragma unroll
-          for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
+            for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
+          }
         }
         // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
         const bool minus = fwd != DAG;
-        switch (dir & 3) {
-          case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
-          case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
-          case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
-          default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
+        if constexpr (P::SCALED) {
+          const R sc = scl[k];
+          switch (dir & 3) {
+            case 0: if (minus) hop_one_scaled<0, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<0, -1>(psi[k], sc, U + dir * 9, acc); break;
+            case 1: if (minus) hop_one_scaled<1, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<1, -1>(psi[k], sc, U + dir * 9, acc); break;
+            case 2: if (minus) hop_one_scaled<2, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<2, -1>(psi[k], sc, U + dir * 9, acc); break;
+            default: if (minus) hop_one_scaled<3, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<3, -1>(psi[k], sc, U + dir * 9, acc); break;
+          }
+        } else {
+          switch (dir & 3) {
+            case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
+            case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
+            case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
+            default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
+          }
         }
       }
     }

@@ -80,8 +80,11 @@ def test_sweep_fp64_parity(sweep_env, case, opi):
 @pytest.mark.parametrize("prec", [odwf.FP32, odwf.FP16S, odwf.BF16S], ids=["fp32", "fp16s", "bf16s"])
 def test_sweep_reduced_precision_matches_one_t_kernel(sweep_env, prec):
     """The sweep sums the hop terms in the order of the one-t-per-block kernel:
-    the two agree far below the format's error against FP64, and both stay
-    within the stated bound."""
+    in FP32 the two agree to rounding (1e-3 of the format's bound).  For the
+    scaled formats the one-t kernel applies the per-site scale after the link
+    product and the sweep before it, and the FP16/BF16 re-quantisation of the
+    output turns that rounding difference into occasional one-ulp changes: they
+    agree to 5 % of the format's error bound.  Both stay within the bound."""
     case = CASES[0]
     U, w, lat, sol, psi, psid = _setup(case)
     bound = {odwf.FP32: 1e-5, odwf.FP16S: 4e-3, odwf.BF16S: 3e-2}[prec]
@@ -96,7 +99,7 @@ def test_sweep_reduced_precision_matches_one_t_kernel(sweep_env, prec):
         d = _relerr(b[0], a[0])
         print(f"{odwf.PREC_NAMES[prec]} op {op}: one-t {ea:.3e} sweep {eb:.3e} sweep vs one-t {d:.3e}")
         assert eb <= bound and ea <= bound
-        assert d <= 1e-3 * bound
+        assert d <= (1e-3 if prec == odwf.FP32 else 5e-2) * bound
 
 
 @pytest.mark.parametrize("inner", [odwf.FP64, odwf.FP32], ids=["fp64", "fp32"])
