@@ -1,8 +1,11 @@
 """Summaries of rocprofv3 CSV output for the profiles/ folder.
 
-  python -m paper_1811_08095_amd.profsum ktrace DIR OUT --cmd "..."
+  python -m paper_1811_08095_amd.profsum ktrace DIR OUT --cmd "..." [--cycle REGEX --cycle-len N]
       per-kernel call count, average and share from the kernel-trace
-      statistics (run_kernel_stats.csv)
+      statistics (run_kernel_stats.csv); with --cycle, the dispatches whose
+      names match REGEX are taken in start order as a repeating sequence of N
+      launches (one solver iteration) and the median duration of each
+      position in it is listed (run_kernel_trace.csv)
 
   python -m paper_1811_08095_amd.profsum traffic --fetch DIR1 --write DIR2 \
       --kernel REGEX --copy-bytes N --workload KEY OUT --cmd-fetch "..." --cmd-write "..."
@@ -69,8 +72,35 @@ def cmd_ktrace(a):
              "# avg_us = AverageNs / 1000; top kernels by total time", ""]
     for name, calls, avg_us, pct in rows[:a.top]:
         lines.append(f"{name[:110]:110s} calls={calls:6d} avg_us={avg_us:10.2f} pct={pct:6.2f}")
+    if a.cycle:
+        lines += [""] + cycle_lines(a.dir, a.cycle, a.cycle_len, a.cycle_skip)
     open(a.out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def cycle_lines(d, regex, n, skip):
+    """Median duration per position of a repeating launch sequence."""
+    rx = re.compile(regex)
+    rows = [r for r in csv.DictReader(open(_find(d, "kernel_trace.csv"))) if rx.search(r["Kernel_Name"])]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[skip * n:]
+    ncyc = len(rows) // n
+    if ncyc == 0:
+        raise RuntimeError(f"fewer than {n} dispatches matching {regex} after the skipped cycles")
+    out = [f"# launch sequence: dispatches matching {regex!r} in start order, taken as {ncyc} cycles of "
+           f"{n} (the first {skip} skipped); median duration per position", ""]
+    total = 0.0
+    for k in range(n):
+        names = collections.Counter(rows[c * n + k]["Kernel_Name"] for c in range(ncyc))
+        durs = sorted((int(rows[c * n + k]["End_Timestamp"]) - int(rows[c * n + k]["Start_Timestamp"])) / 1e3
+                      for c in range(ncyc))
+        med = durs[len(durs) // 2]
+        total += med
+        name, cnt = names.most_common(1)[0]
+        tag = "" if cnt == ncyc else f" (position holds {len(names)} kernels; {cnt} of {ncyc} are this one)"
+        out.append(f"position {k}: {name[:100]:100s} median_us={med:10.2f}{tag}")
+    out.append(f"sum of the medians per cycle: {total:.2f} us")
+    return out
 
 
 def _copy_factor(vals, nbytes):
@@ -143,6 +173,9 @@ def main(argv=None):
     k.add_argument("--cmd", required=True)
     k.add_argument("--title", default="")
     k.add_argument("--top", type=int, default=20)
+    k.add_argument("--cycle", default="")
+    k.add_argument("--cycle-len", type=int, default=5)
+    k.add_argument("--cycle-skip", type=int, default=1)
     t = sub.add_parser("traffic")
     t.add_argument("out")
     t.add_argument("--fetch", required=True)

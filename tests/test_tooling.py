@@ -47,3 +47,25 @@ def test_traffic_summary_calibration_and_hash_guard(tmp_path):
     stale = out.read_text().replace(profsum.hop_source_hash(), "0000000000000000")
     out.write_text(stale)
     assert profsum.read_traffic(str(out), "wk") is None
+
+
+def test_launch_cycle_summary(tmp_path):
+    # two warm-up-like cycles, then three regular ones; an unrelated kernel in between
+    seq = ["k1", "k1", "k2", "k2", "xp"]
+    rows, t = [], 0
+    for c in range(5):
+        for k, n in enumerate(seq):
+            rows.append((f"hop<{n}>" if n != "xp" else "xpby", t, t + 1000 * (k + 1) * (3 if c == 0 else 1)))
+            t += 10_000
+        rows.append(("other", t, t + 50_000))
+        t += 60_000
+    with open(tmp_path / "run_kernel_trace.csv", "w") as f:
+        f.write("Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for n, a, b in reversed(rows):  # order must come from the timestamps
+            f.write(f'"{n}",{a},{b}\n')
+    out = profsum.cycle_lines(str(tmp_path), r"hop<|xpby", 5, 1)
+    pos = [ln for ln in out if ln.startswith("position")]
+    assert len(pos) == 5
+    assert "hop<k1>" in pos[0] and "xpby" in pos[4]
+    assert [float(ln.split("median_us=")[1].split()[0]) for ln in pos] == [1.0, 2.0, 3.0, 4.0, 5.0]
+    assert out[-1].endswith("15.00 us")
