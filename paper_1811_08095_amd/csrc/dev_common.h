@@ -433,6 +433,144 @@ __device__ __forceinline__ void m5_run_lds(const M5Prog& prog, cpx<R>* col, int 
 }
 
 // ---------------------------------------------------------------------------
+// the same programs with the column spread over lanes: for N_s = 16 the 16
+// slices of one (site, right-hand side) are the 16 lanes of one DPP row, so
+// every lane keeps its own slice of all 12 components in registers and the
+// fifth-dimension couplings become cross-lane moves inside the row.  The
+// bidiagonal products need the neighbouring slice (a row rotation); the cyclic
+// bidiagonal solves are first-order linear recurrences x_u = a_u x_{u-1} + b_u,
+// solved by a log2(16)-step scan over the affine maps (a, b), closed around the
+// cycle with x_last = b_last / (1 - a_last) and one broadcast in the row.
+// FP32 arithmetic only; chirality + runs in slice order, chirality - in the
+// mirrored order (as in m5_run).
+// ---------------------------------------------------------------------------
+#ifndef ODWF_LANE_PASS
+#define ODWF_LANE_PASS 1
+#endif
+template <class R, int NS>
+struct LanePass {
+  static constexpr bool on = ODWF_LANE_PASS && sizeof(R) == 4 && NS == 16;
+};
+
+// DPP16 row controls: lane i reads lane i - n (SHR), i + n (SHL) or (i - n) mod 16 (ROR)
+constexpr int DPP_SHL(int n) { return 0x100 + n; }
+constexpr int DPP_SHR(int n) { return 0x110 + n; }
+constexpr int DPP_ROR(int n) { return 0x120 + n; }
+
+// value of v in the lane given by CTRL; lanes whose source lies outside the row get `old`
+template <int CTRL>
+__device__ __forceinline__ float row_move(float old, float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// value of v in lane 15 (LAST) or lane 0 of the lane's row
+template <bool LAST>
+__device__ __forceinline__ float row_bcast(float v) {
+  // ds_swizzle bit-mask mode on groups of 32: lane' = (lane & 0x10) | (LAST ? 0xF : 0)
+  constexpr int pat = 0x10 | ((LAST ? 0x0F : 0x00) << 5);
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pat));
+}
+
+// y[c0 .. c0+5] = d y + e y_nb, with y_nb the value of the neighbouring slice
+template <int CTRL>
+__device__ __forceinline__ void lane_mul(cpx<float> (&y)[12], int c0, float d, float e) {
+#pragma unroll
+  for (int c = c0; c < c0 + 6; c++) {
+    const float nr = row_move<CTRL>(0.f, y[c].re), ni = row_move<CTRL>(0.f, y[c].im);
+    y[c] = {d * y[c].re + e * nr, d * y[c].im + e * ni};
+  }
+}
+
+// y[c0 .. c0+5] <- solution of x_u = a x_{u-1} + b_u (b_u = y on entry) around
+// the cycle; SHIFT is the scan direction in lanes, LAST the lane of the final
+// element in scan order
+template <bool DOWN, bool LAST>
+__device__ __forceinline__ void lane_solve(cpx<float> (&y)[12], int c0, float a) {
+#pragma unroll
+  for (int k = 1; k < 16; k <<= 1) {
+    float pa;
+#pragma unroll
+    for (int c = c0; c < c0 + 6; c++) {
+      float pr, pi;
+      if (k == 1) {
+        pr = DOWN ? row_move<DPP_SHR(1)>(0.f, y[c].re) : row_move<DPP_SHL(1)>(0.f, y[c].re);
+        pi = DOWN ? row_move<DPP_SHR(1)>(0.f, y[c].im) : row_move<DPP_SHL(1)>(0.f, y[c].im);
+      } else if (k == 2) {
+        pr = DOWN ? row_move<DPP_SHR(2)>(0.f, y[c].re) : row_move<DPP_SHL(2)>(0.f, y[c].re);
+        pi = DOWN ? row_move<DPP_SHR(2)>(0.f, y[c].im) : row_move<DPP_SHL(2)>(0.f, y[c].im);
+      } else if (k == 4) {
+        pr = DOWN ? row_move<DPP_SHR(4)>(0.f, y[c].re) : row_move<DPP_SHL(4)>(0.f, y[c].re);
+        pi = DOWN ? row_move<DPP_SHR(4)>(0.f, y[c].im) : row_move<DPP_SHL(4)>(0.f, y[c].im);
+      } else {
+        pr = DOWN ? row_move<DPP_SHR(8)>(0.f, y[c].re) : row_move<DPP_SHL(8)>(0.f, y[c].re);
+        pi = DOWN ? row_move<DPP_SHR(8)>(0.f, y[c].im) : row_move<DPP_SHL(8)>(0.f, y[c].im);
+      }
+      y[c] = {y[c].re + a * pr, y[c].im + a * pi};
+    }
+    if (k == 1) pa = DOWN ? row_move<DPP_SHR(1)>(1.f, a) : row_move<DPP_SHL(1)>(1.f, a);
+    else if (k == 2) pa = DOWN ? row_move<DPP_SHR(2)>(1.f, a) : row_move<DPP_SHL(2)>(1.f, a);
+    else if (k == 4) pa = DOWN ? row_move<DPP_SHR(4)>(1.f, a) : row_move<DPP_SHL(4)>(1.f, a);
+    else pa = DOWN ? row_move<DPP_SHR(8)>(1.f, a) : row_move<DPP_SHL(8)>(1.f, a);
+    a *= pa;
+  }
+  // a is now the product of the step factors up to this lane; close the cycle
+  const float g = 1.f / (1.f - a);
+#pragma unroll
+  for (int c = c0; c < c0 + 6; c++) {
+    const float xr = row_bcast<LAST>(g * y[c].re), xi = row_bcast<LAST>(g * y[c].im);
+    y[c] = {y[c].re + a * xr, y[c].im + a * xi};
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void m5_run_lanes(const M5Prog& prog, cpx<float> (&y)[12],
+                                             const float* __restrict__ cf, float kappa, int s) {
+  static_assert(NS == 16, "one DPP row per column");
+  const int up = s, um = NS - 1 - s;  // chirality-local slice index, chirality + and -
+  const float* cfm = cf + NCOEF * NS;
+  for (int k = 0; k < prog.n; k++) {
+    const M5Op op = prog.op[k];
+    const float dp = cf[op.d * NS + up], dm = cfm[op.d * NS + um];
+    float ep = cf[op.e * NS + up], em = cfm[op.e * NS + um];
+    switch (op.type) {
+      case M5_SCALE: {
+#pragma unroll
+        for (int c = 0; c < 12; c++) y[c] = cscale(c < 6 ? dp : dm, y[c]);
+      } break;
+      case M5_MUL_LO: {  // local u - 1: lane s - 1 (chirality +), s + 1 (chirality -)
+        if (up == 0) ep *= kappa;
+        if (um == 0) em *= kappa;
+        lane_mul<DPP_ROR(1)>(y, 0, dp, ep);
+        lane_mul<DPP_ROR(15)>(y, 6, dm, em);
+      } break;
+      case M5_MUL_UP: {  // local u + 1: lane s + 1 (chirality +), s - 1 (chirality -)
+        if (up == NS - 1) ep *= kappa;
+        if (um == NS - 1) em *= kappa;
+        lane_mul<DPP_ROR(15)>(y, 0, dp, ep);
+        lane_mul<DPP_ROR(1)>(y, 6, dm, em);
+      } break;
+      case M5_SOLVE_LO: {  // x_u = d_u (y_u - e_u x_{u-1}), x_{-1} = x_{N-1} with e_0 -> kappa e_0
+        if (up == 0) ep *= kappa;
+        if (um == 0) em *= kappa;
+#pragma unroll
+        for (int c = 0; c < 12; c++) y[c] = cscale(c < 6 ? dp : dm, y[c]);
+        lane_solve<true, true>(y, 0, -dp * ep);    // chirality +: from lane s - 1, ends at lane 15
+        lane_solve<false, false>(y, 6, -dm * em);  // chirality -: from lane s + 1, ends at lane 0
+      } break;
+      case M5_SOLVE_UP: {  // x_u = d_u (y_u - e_u x_{u+1}), x_N = x_0 with e_{N-1} -> kappa e_{N-1}
+        if (up == NS - 1) ep *= kappa;
+        if (um == NS - 1) em *= kappa;
+#pragma unroll
+        for (int c = 0; c < 12; c++) y[c] = cscale(c < 6 ? dp : dm, y[c]);
+        lane_solve<false, false>(y, 0, -dp * ep);  // chirality +: from lane s + 1, ends at lane 0
+        lane_solve<true, true>(y, 6, -dm * em);    // chirality -: from lane s - 1, ends at lane 15
+      } break;
+      default: break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column pass: buf holds [site][rhs][12 components][NS + 1] values; every
 // column (site, rhs, component) of NS values is transformed by prog.  Items
 // are ordered (chirality, site, rhs, component-of-chirality) with each

@@ -265,6 +265,11 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
   constexpr int NSP = NS + 1;
   const int nrhs = a.nrhs;
   auto column_pass = [&](const M5Prog& prog, cpx<R>(&v)[12]) {
+    if constexpr (LanePass<R, NS>::on) {
+      // the column lives in the lanes of this (site, rhs): no LDS, no barrier
+      m5_run_lanes<NS>(prog, v, coef, kap[r], s);
+      return;
+    }
     __syncthreads();
     if (valid) {
       cpx<R>* b = buf + ((size_t)(sl * nrhs + r) * 12) * NSP + s;
@@ -352,14 +357,16 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
   return nval;
 }
 
-// minimum waves per SIMD the register allocation must allow
-template <class P, bool PLAIN>
+// minimum waves per SIMD the register allocation must allow (the fused FP32
+// kernels fit four when their column programs run across lanes)
+template <class P, int NS, bool PLAIN>
 struct HopWaves {
-  static constexpr int W = sizeof(typename P::real) == 8 ? 2 : (PLAIN ? 4 : 2);
+  static constexpr int W =
+      sizeof(typename P::real) == 8 ? 2 : ((PLAIN || LanePass<typename P::real, NS>::on) ? 4 : 2);
 };
 
 template <class P, int NS, bool DAG, bool PLAIN>
-__global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const HopArgs a) {
+__global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(const HopArgs a) {
   using R = typename P::real;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nrhs = a.nrhs;
@@ -396,7 +403,8 @@ __global__ void __launch_bounds__(256, (HopWaves<P, PLAIN>::W)) hop_kernel(const
   const bool has_x = !PLAIN && a.xin != nullptr;
   // x term with its own fifth-dimension program: transform it in LDS before the
   // hop, so no column pass runs while the hop accumulators are live
-  const bool x_first = has_x && a.prog_x.n > 0;
+  // (with the lane-parallel programs the x term is transformed after the hop instead)
+  const bool x_first = has_x && a.prog_x.n > 0 && !LanePass<R, NS>::on;
   if (x_first) {
     if (valid) {
       load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
