@@ -507,8 +507,12 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
     return;
   }
 
-  const double nval =
-      fused_tail<P, NS>(a, acc, valid, j, sl, r, s, nsb, buf, coef, kap, x_first ? X_LDS : X_LOAD);
+  // the own-site index again from the block-uniform first site: cheaper than
+  // keeping the 64-bit index live through the hop (which spills at 4 waves)
+  int slr = sl;
+  asm volatile("" : "+v"(slr));
+  const double nval = fused_tail<P, NS>(a, acc, valid, j0 + slr, sl, r, s, nsb, buf, coef, kap,
+                                        x_first ? X_LDS : X_LOAD);
   if (a.partial) {
     red[tid] = valid ? nval : 0.0;
     block_reduce_rhs(
