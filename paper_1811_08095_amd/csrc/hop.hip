@@ -287,7 +287,10 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
   };
 
   if (a.prog_h.n > 0) column_pass(a.prog_h, acc);  // never together with X_LDS
-  cpx<R> xv[12];
+  const int cgmode = a.partial ? (a.cg_r ? 2 : (a.cg_p ? 3 : 1)) : 0;
+  const bool cg_update = cgmode == 2 && valid && a.scal[r].active;
+  cpx<R> xv[12], rv[12];
+  bool r_loaded = false;
   const bool has_x = a.xin != nullptr;
   if (has_x) {
     if (xmode == X_LDS) {  // transformed before the hop, still in the column buffer
@@ -298,6 +301,13 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
       }
     } else {
       if (valid) load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+      if constexpr (LanePass<R, NS>::on && !P::SCALED) {
+        // the CG residual travels with the x term: one memory round trip fewer
+        if (cg_update) {
+          load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+          r_loaded = true;
+        }
+      }
       if (a.prog_x.n > 0) column_pass(a.prog_x, xv);
     }
   }
@@ -311,7 +321,6 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
     for (int c = 0; c < 12; c++) acc[c] = cscale(ch, acc[c]);
   }
 
-  const int cgmode = a.partial ? (a.cg_r ? 2 : (a.cg_p ? 3 : 1)) : 0;
   double nval = 0.0;
   if (cgmode == 1 && valid) {
 #pragma unroll
@@ -329,11 +338,10 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
     }
   }
   if (cgmode == 2) {
-    if (valid && a.scal[r].active) {
+    if (cg_update) {
       const R al = (R)a.scal[r].alpha;
       {  // r -= alpha N p, |r|^2
-        cpx<R> rv[12];
-        load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+        if (!r_loaded) load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
 #pragma unroll
         for (int c = 0; c < 12; c++) {
           rv[c] = csub(rv[c], cscale(al, acc[c]));
