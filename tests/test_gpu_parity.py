@@ -120,3 +120,17 @@ def test_rhs_independence():
     for r, mq in enumerate(MASSES):
         single = sol.apply(odwf.OP_SCHUR_NORMAL, psid[r:r + 1].contiguous(), [mq]).cpu().numpy()[0]
         np.testing.assert_allclose(single, multi[r], rtol=0, atol=1e-14 * np.abs(multi[r]).max())
+
+
+@pytest.mark.parametrize("prec", [odwf.FP32, odwf.FP16S], ids=["fp32", "fp16s"])
+def test_rhs_independence_ns16(prec):
+    """N_s = 16 in reduced precision, where the fifth-dimension programs of the
+    fused kernels run across the lanes of one (site, rhs): a multi-RHS launch
+    equals the single-RHS launches bit for bit, so no lane exchange crosses
+    from one right-hand side (or site) to another; ragged final block included."""
+    U, w, lat, sol, psi, psid = _setup(CASES[3])
+    for op in (odwf.OP_SCHUR_NORMAL, odwf.OP_D, odwf.OP_DDAG):
+        multi = sol.apply(op, psid, MASSES, prec=prec).cpu().numpy()
+        for r, mq in enumerate(MASSES):
+            single = sol.apply(op, psid[r:r + 1].contiguous(), [mq], prec=prec).cpu().numpy()[0]
+            assert np.array_equal(single, multi[r]), (op, mq)
