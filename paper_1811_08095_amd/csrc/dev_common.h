@@ -482,8 +482,8 @@ __device__ __forceinline__ void lane_mul(cpx<float> (&y)[12], int c0, float d, f
 }
 
 // y[c0 .. c0+5] <- solution of x_u = a x_{u-1} + b_u (b_u = y on entry) around
-// the cycle; SHIFT is the scan direction in lanes, LAST the lane of the final
-// element in scan order
+// the cycle; DOWN: element u - 1 sits in the next lower lane (else the next
+// higher one); LAST: the final element in scan order sits in lane 15 (else 0)
 template <bool DOWN, bool LAST>
 __device__ __forceinline__ void lane_solve(cpx<float> (&y)[12], int c0, float a) {
 #pragma unroll

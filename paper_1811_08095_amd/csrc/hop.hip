@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   }
 
   // the own-site index again from the block-uniform first site: cheaper than
-  // keeping the 64-bit index live through the hop (which spills at 4 waves)
+  // keeping the 64-bit index live through the hop (which spills at 4 waves);
+  // the empty asm stops the compiler from reusing the value computed earlier
   int slr = sl;
   asm volatile("" : "+v"(slr));
   const double nval = fused_tail<P, NS>(a, acc, valid, j0 + slr, sl, r, s, nsb, buf, coef, kap,
