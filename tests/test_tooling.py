@@ -69,3 +69,24 @@ def test_launch_cycle_summary(tmp_path):
     assert "hop<k1>" in pos[0] and "xpby" in pos[4]
     assert [float(ln.split("median_us=")[1].split()[0]) for ln in pos] == [1.0, 2.0, 3.0, 4.0, 5.0]
     assert out[-1].endswith("15.00 us")
+
+
+def test_committed_bench_line_keeps_the_contract():
+    """The recorded bench line carries every field of the benchmark contract,
+    with the roofline and CPU-baseline objects complete and self-consistent."""
+    import json
+    d = json.load(open(os.path.join(ROOT, "profiles", "bench_64x64x64x64_Ns16_mixed_cg.json")))
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["unit"] == "GB/s" and d["higher_is_better"] is True
+    assert "workload" in d["config"] and "model" not in d["config"]
+    rf = d["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in rf, k
+    assert rf["bound"] == "hbm" and rf["peak"] == 8000.0 and rf["unit"] == "GB/s"
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
+    cb = d["cpu_baseline"]
+    for k in ("value", "unit", "cores", "kind", "sample"):
+        assert k in cb, k
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1
