@@ -168,6 +168,13 @@ odwf_status odwf_solve(odwf_solver s, odwf_mode mode, const double* mq, const do
                        int nrhs, odwf_prec inner, int maxiter, const void* b, void* x,
                        int use_x0, odwf_stats* stats, void* stream);
 
+/* Allocate now the workspaces odwf_solve uses on `stream` for nrhs right-hand
+ * sides (at most one launch's worth, 256 / Ns, is held) in precision `inner`,
+ * so that a later solve does no device allocation of its own.  Workspaces are
+ * kept per stream until the solver is destroyed.  ODWF_ENOMEM if they do not
+ * fit. */
+odwf_status odwf_solver_reserve(odwf_solver s, int nrhs, odwf_prec inner, void* stream);
+
 /* Device bytes odwf_solve needs beyond the resident gauge copies for a
  * lattice of extents dims (workspace only; the caller's b and x excluded). */
 odwf_status odwf_footprint(const int dims[4], int Ns, int nrhs, odwf_prec inner, size_t* bytes);
@@ -215,7 +222,12 @@ void odwf_batch_destroy(odwf_batch bt);
  * around every hopping-kernel launch.  enable != 0 turns it on (and clears the
  * counters).  odwf_profile_read synchronises the recorded events and returns
  * the number of hopping launches, their summed duration in milliseconds and
- * their summed algorithmic bytes (spinor reads and writes plus link reads). */
+ * their summed algorithmic bytes (spinor reads and writes plus link reads,
+ * plus the vector streams a launch carries for a fused CG step).  Batch-engine
+ * launches restricted to the active slots count with the bytes of every slot
+ * (exact while all slots are active); the batch's FP64 reliable-update
+ * launches, which run only for slots that requested an update, are not
+ * counted. */
 odwf_status odwf_profile_enable(int enable);
 odwf_status odwf_profile_read(long long* launches, double* ms, double* bytes);
 

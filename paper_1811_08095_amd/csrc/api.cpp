@@ -212,15 +212,25 @@ static odwf_status apply_chunk(odwf_solver S, odwf_op op, const double* mq, int 
   c.prec = prec;
   c.nrhs = nrhs;
   for (int r = 0; r < MAXRHS; r++) c.kappa[r] = r < nrhs ? -mq[r0 + r] / (2.0 * S->m0) : 0.0;
-  HV ie = W.half("ap.ie", g.h, nrhs, Ns, prec), io = W.half("ap.io", g.h, nrhs, Ns, prec);
-  HV oe = W.half("ap.oe", g.h, nrhs, Ns, prec), oo = W.half("ap.oo", g.h, nrhs, Ns, prec);
-  HV te = W.half("ap.te", g.h, nrhs, Ns, prec), to = W.half("ap.to", g.h, nrhs, Ns, prec);
-  if (!ie.d || !io.d || !oe.d || !oo.d || !te.d || !to.d) {
+  // the half fields each operator uses: inputs (even, odd), outputs, scratch
+  const bool full = op == ODWF_OP_D || op == ODWF_OP_DDAG || op == ODWF_OP_DDAGD;
+  const bool need_ie = op != ODWF_OP_HOP_EO, need_io = op != ODWF_OP_HOP_OE && op < ODWF_OP_SCHUR;
+  const bool need_oe = op != ODWF_OP_HOP_OE, need_oo = op == ODWF_OP_HOP_OE || op == ODWF_OP_M5INV || full;
+  const bool need_te = full || op == ODWF_OP_SCHUR_DAG || op == ODWF_OP_SCHUR_NORMAL;
+  const bool need_to = full || op >= ODWF_OP_SCHUR;
+  auto half = [&](bool need, const char* name) {
+    return need ? W.half(name, g.h, nrhs, Ns, prec) : HV();
+  };
+  HV ie = half(need_ie, "ap.ie"), io = half(need_io, "ap.io");
+  HV oe = half(need_oe, "ap.oe"), oo = half(need_oo, "ap.oo");
+  HV te = half(need_te, "ap.te"), to = half(need_to, "ap.to");
+  if ((need_ie && !ie.d) || (need_io && !io.d) || (need_oe && !oe.d) || (need_oo && !oo.d) ||
+      (need_te && !te.d) || (need_to && !to.d)) {
     set_error("odwf_apply: out of device memory for workspaces");
     return ODWF_ENOMEM;
   }
-  HIPCHK(launch_pack_spinor(prec, in, r0, ie.d, ie.sc, 0, nrhs, Ns, g, st));
-  HIPCHK(launch_pack_spinor(prec, in, r0, io.d, io.sc, 1, nrhs, Ns, g, st));
+  if (need_ie) HIPCHK(launch_pack_spinor(prec, in, r0, ie.d, ie.sc, 0, nrhs, Ns, g, st));
+  if (need_io) HIPCHK(launch_pack_spinor(prec, in, r0, io.d, io.sc, 1, nrhs, Ns, g, st));
   bool have_e = true, have_o = true;
   HopOpt o;
   switch (op) {
@@ -322,6 +332,22 @@ extern "C" odwf_status odwf_solve(odwf_solver S, odwf_mode mode, const double* m
     if (s != ODWF_OK && worst == ODWF_OK) worst = s;
   }
   return worst;
+}
+
+extern "C" odwf_status odwf_solver_reserve(odwf_solver S, int nrhs, odwf_prec inner, void* stream) {
+  REQUIRE(S, "odwf_solver_reserve: null solver");
+  REQUIRE(nrhs >= 1, "odwf_solver_reserve: nrhs must be >= 1");
+  REQUIRE(inner >= ODWF_FP64 && inner <= ODWF_BF16S, "odwf_solver_reserve: bad inner precision");
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  SolveBufs B;
+  const int n = std::min(nrhs, max_rhs_per_launch(S->Ns));
+  if (!solve_buffers(S->workspace(st), S->lat->g.h, n, S->Ns, (int)inner, B)) {
+    set_error("odwf_solver_reserve: out of device memory");
+    return ODWF_ENOMEM;
+  }
+  return ODWF_OK;
 }
 
 extern "C" odwf_status odwf_footprint(const int dims[4], int Ns, int nrhs, odwf_prec inner,

@@ -102,11 +102,22 @@ extern "C" odwf_status odwf_batch_create(odwf_solver S, int max_slots, odwf_prec
   B->t = W.half("t", h, k, Ns, inner);
   B->v = W.half("v", h, k, Ns, inner);
   if ((int)inner != PREC64) B->x = W.half("x", h, k, Ns, inner);
-  B->s_e0 = W.half("s_e0", h, 1, Ns, PREC64);
-  B->s_e1 = W.half("s_e1", h, 1, Ns, PREC64);
-  B->s_e2 = W.half("s_e2", h, 1, Ns, PREC64);
-  B->s_o0 = W.half("s_o0", h, 1, Ns, PREC64);
-  B->s_bo = W.half("s_bo", h, 1, Ns, PREC64);
+  if (k == 1) {
+    // one slot: admission and retirement work in the slot's own fields (same
+    // layout); every step of both sequences reads and writes them in an order
+    // in which no value is overwritten before its last use
+    B->s_e0 = B->f;
+    B->s_e1 = B->y;
+    B->s_e2 = B->e2;
+    B->s_o0 = B->o0;
+    B->s_bo = B->bo;
+  } else {
+    B->s_e0 = W.half("s_e0", h, 1, Ns, PREC64);
+    B->s_e1 = W.half("s_e1", h, 1, Ns, PREC64);
+    B->s_e2 = W.half("s_e2", h, 1, Ns, PREC64);
+    B->s_o0 = W.half("s_o0", h, 1, Ns, PREC64);
+    B->s_bo = W.half("s_bo", h, 1, Ns, PREC64);
+  }
   const int nb = std::max(hop_nblocks((int)h, k, Ns), vec_nblocks(h, k, Ns));
   B->partial = (double*)W.get("partial", partial_bytes(nb, k));
   B->dscal = (CGScal*)W.get("scal", MAXRHS * sizeof(CGScal));
@@ -177,10 +188,12 @@ extern "C" odwf_status odwf_batch_admit(odwf_batch B, const void* b, double mq, 
   kp.po = prog_ainv();
   BCHK(hop(c1, 0, 0, B->s_o0, &B->s_e1, kp));
   BCHK(apply_schur_dag(c1, B->s_e1, B->s_e2, B->s_o0, B->s_e0));
-  // scatter into the slot
-  BCHK(launch_vec_copy_rhs(PREC64, B->s_e0.d, nullptr, 1, 0, PREC64, B->f.d, nullptr, B->k, q, h, Ns, st));
+  // scatter into the slot (a one-slot engine prepared f and bo in place)
+  if (B->s_e0.d != B->f.d)
+    BCHK(launch_vec_copy_rhs(PREC64, B->s_e0.d, nullptr, 1, 0, PREC64, B->f.d, nullptr, B->k, q, h, Ns, st));
   BCHK(launch_vec_copy_rhs(PREC64, nullptr, nullptr, 1, 0, PREC64, B->y.d, nullptr, B->k, q, h, Ns, st));
-  BCHK(launch_vec_copy_rhs(PREC64, B->s_bo.d, nullptr, 1, 0, PREC64, B->bo.d, nullptr, B->k, q, h, Ns, st));
+  if (B->s_bo.d != B->bo.d)
+    BCHK(launch_vec_copy_rhs(PREC64, B->s_bo.d, nullptr, 1, 0, PREC64, B->bo.d, nullptr, B->k, q, h, Ns, st));
   BCHK(launch_vec_copy_rhs(PREC64, B->s_e0.d, nullptr, 1, 0, B->inner, B->r.d, B->r.sc, B->k, q, h, Ns, st));
   BCHK(launch_vec_copy_rhs(PREC64, B->s_e0.d, nullptr, 1, 0, B->inner, B->p.d, B->p.sc, B->k, q, h, Ns, st));
   if (B->inner != PREC64)
@@ -311,8 +324,10 @@ extern "C" odwf_status odwf_batch_retire(odwf_batch B, int slot, void* x, odwf_s
   const int Ns = S->Ns;
   double kap1[MAXRHS] = {-B->mq[slot] / (2.0 * S->m0)};
   OpCtx c1 = ctx_of(B, st, PREC64, 1, kap1);
-  BCHK(launch_vec_copy_rhs(PREC64, B->y.d, nullptr, B->k, slot, PREC64, B->s_e1.d, nullptr, 1, 0, h, Ns, st));
-  BCHK(launch_vec_copy_rhs(PREC64, B->bo.d, nullptr, B->k, slot, PREC64, B->s_bo.d, nullptr, 1, 0, h, Ns, st));
+  if (B->s_e1.d != B->y.d)
+    BCHK(launch_vec_copy_rhs(PREC64, B->y.d, nullptr, B->k, slot, PREC64, B->s_e1.d, nullptr, 1, 0, h, Ns, st));
+  if (B->s_bo.d != B->bo.d)
+    BCHK(launch_vec_copy_rhs(PREC64, B->bo.d, nullptr, B->k, slot, PREC64, B->s_bo.d, nullptr, 1, 0, h, Ns, st));
   // y_o = A^{-1}(b'_o - W_oe y_e), x = (1 + L)^{-1} y
   HopOpt kr;
   kr.x = &B->s_bo;

@@ -177,7 +177,10 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   a.dag = dag;
   for (int d = 0; d < 4; d++) a.L[d] = L->g.L[d];
   traversal(a, c.S->Ns);
-  const bool prof = prof_on() && !o.gate;  // gated launches do partial work
+  // launches gated to the active right-hand sides of a batch are counted with
+  // the bytes of all nrhs (exact while every slot is active); launches gated to
+  // pending reliable updates mostly exit at once and are not counted
+  const bool prof = prof_on() && (!o.gate || o.gate_mode == GATE_ACTIVE);
   if (prof) prof_begin(c.st, (c.prec & 3) * 2 + (dag ? 1 : 0));
   hipError_t e = launch_hop(a, c.prec, c.S->Ns, c.st);
   if (prof) {

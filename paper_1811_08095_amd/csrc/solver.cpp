@@ -166,6 +166,29 @@ size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner) {
   return b;
 }
 
+bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B) {
+  B.e0 = W.half("s.e0", h, nrhs, Ns, PREC64);  // f
+  B.e1 = W.half("s.e1", h, nrhs, Ns, PREC64);  // y
+  B.e2 = W.half("s.e2", h, nrhs, Ns, PREC64);  // FP64 even scratch / residual
+  B.o0 = W.half("s.o0", h, nrhs, Ns, PREC64);  // FP64 odd scratch
+  const int nbmax = std::max(hop_nblocks((int)h, nrhs, Ns), vec_nblocks(h, nrhs, Ns));
+  B.partial = (double*)W.get("s.partial", partial_bytes(nbmax, nrhs));
+  B.scal = (CGScal*)W.get("s.scal", 2 * MAXRHS * sizeof(CGScal));
+  B.res = (double*)W.get("s.res", 4 * MAXRHS * sizeof(double));
+  bool ok = B.e0.d && B.e1.d && B.e2.d && B.o0.d && B.partial && B.scal && B.res;
+  if (inner == PREC64) {
+    B.r = W.half("s.r64", h, nrhs, Ns, PREC64);
+    B.p = W.half("s.p64", h, nrhs, Ns, PREC64);
+    return ok && B.r.d && B.p.d;
+  }
+  B.p = W.half("s.p", h, nrhs, Ns, inner);
+  B.r = W.half("s.r", h, nrhs, Ns, inner);
+  B.x = W.half("s.x", h, nrhs, Ns, inner);
+  B.t = W.half("s.t", h, nrhs, Ns, inner);
+  B.v = W.half("s.v", h, nrhs, Ns, inner);
+  return ok && B.p.d && B.r.d && B.x.d && B.t.d && B.v.d;
+}
+
 // residual f - N y into `res` (which may be the v scratch) and its norm
 // partials; then FIN_INIT on scal
 static hipError_t true_residual(const OpCtx& c64, const HV& f, const HV& y, const HV& t, const HV& v,
@@ -204,19 +227,16 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     }                                                                                   \
   } while (0)
 
-  HV e0 = W.half("s.e0", h, nrhs, Ns, PREC64);  // f
-  HV e1 = W.half("s.e1", h, nrhs, Ns, PREC64);  // y
-  HV e2 = W.half("s.e2", h, nrhs, Ns, PREC64);  // FP64 even scratch / residual
-  HV o0 = W.half("s.o0", h, nrhs, Ns, PREC64);  // FP64 odd scratch
-  const int nbmax = std::max(hop_nblocks((int)h, nrhs, Ns), vec_nblocks(h, nrhs, Ns));
-  double* partial = (double*)W.get("s.partial", partial_bytes(nbmax, nrhs));
-  CGScal* dscal = (CGScal*)W.get("s.scal", 2 * MAXRHS * sizeof(CGScal));
-  CGScal* dscal_out = dscal + MAXRHS;
-  double* dres = (double*)W.get("s.res", 4 * MAXRHS * sizeof(double));
-  if (!e0.d || !e1.d || !e2.d || !o0.d || !partial || !dscal || !dres) {
+  SolveBufs B;
+  if (!solve_buffers(W, h, nrhs, Ns, inner, B)) {
     set_error("odwf_solve: out of device memory for workspaces");
     return ODWF_ENOMEM;
   }
+  HV e0 = B.e0, e1 = B.e1, e2 = B.e2, o0 = B.o0;
+  double* partial = B.partial;
+  CGScal* dscal = B.scal;
+  CGScal* dscal_out = dscal + MAXRHS;
+  double* dres = B.res;
   int nb_vec = 0;
 
   // ---- right-hand side f of the iterated system, initial guess y ----------
@@ -286,11 +306,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
   };
 
   if (inner == PREC64) {
-    HV r = W.half("s.r64", h, nrhs, Ns, PREC64), p = W.half("s.p64", h, nrhs, Ns, PREC64);
-    if (!r.d || !p.d) {
-      set_error("odwf_solve: out of device memory for workspaces");
-      return ODWF_ENOMEM;
-    }
+    HV r = B.r, p = B.p;
     CHK(init_residual(dscal));
     CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, h, nrhs, Ns, st));
     CHK(launch_vec_convert(PREC64, r.d, nullptr, PREC64, p.d, nullptr, 0, h, nrhs, Ns, st));
@@ -318,13 +334,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     }
     for (int q = 0; q < nrhs; q++) inner_iters[q] = cur[q].iters;
   } else if (inner == PREC32) {
-    HV p = W.half("s.p", h, nrhs, Ns, inner), rr = W.half("s.r", h, nrhs, Ns, inner);
-    HV xs = W.half("s.x", h, nrhs, Ns, inner), t = W.half("s.t", h, nrhs, Ns, inner);
-    HV v = W.half("s.v", h, nrhs, Ns, inner);
-    if (!p.d || !rr.d || !xs.d || !t.d || !v.d) {
-      set_error("odwf_solve: out of device memory for workspaces");
-      return ODWF_ENOMEM;
-    }
+    HV p = B.p, rr = B.r, xs = B.x, t = B.t, v = B.v;
     CHK(init_residual(dscal));
     CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, h, nrhs, Ns, st));
     CHK(launch_vec_convert(inner, rr.d, rr.sc, inner, p.d, p.sc, 0, h, nrhs, Ns, st));
@@ -356,13 +366,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     for (int q = 0; q < nrhs; q++) inner_iters[q] = cur[q].iters;
   } else {
     // defect correction around a half/bfloat16 inner CG
-    HV p = W.half("s.p", h, nrhs, Ns, inner), rr = W.half("s.r", h, nrhs, Ns, inner);
-    HV xs = W.half("s.x", h, nrhs, Ns, inner), t = W.half("s.t", h, nrhs, Ns, inner);
-    HV v = W.half("s.v", h, nrhs, Ns, inner);
-    if (!p.d || !rr.d || !xs.d || !t.d || !v.d) {
-      set_error("odwf_solve: out of device memory for workspaces");
-      return ODWF_ENOMEM;
-    }
+    HV p = B.p, rr = B.r, xs = B.x, t = B.t, v = B.v;
     const double tol_in = inner == PREC16 ? 5e-3 : 2e-2;
     CHK(init_residual(dscal_out));
     CHK(read_scal(dscal_out, cur, nrhs, st));

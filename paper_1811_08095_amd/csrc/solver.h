@@ -33,4 +33,15 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
 
 size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner);
 
+// device buffers of a solve chunk of nrhs right-hand sides (named workspace
+// entries, allocated on first use and kept)
+struct SolveBufs {
+  HV e0, e1, e2, o0;  // FP64: f, y, even scratch, odd scratch
+  HV r, p, x, t, v;   // inner precision (FP64: r, p only)
+  double* partial = nullptr;
+  CGScal* scal = nullptr;
+  double* res = nullptr;
+};
+bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B);
+
 }  // namespace odwf

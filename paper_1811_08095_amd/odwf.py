@@ -58,6 +58,7 @@ SYMBOLS = {
     "odwf_solver_destroy": ([_vp], None),
     "odwf_apply": ([_vp, _i, _dp, _i, _i, _vp, _vp, _vp], _i),
     "odwf_solve": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(Stats), _vp], _i),
+    "odwf_solver_reserve": ([_vp, _i, _i, _vp], _i),
     "odwf_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
     "odwf_zolotarev_omega": ([_i, _d, _d, _dp], _i),
     "odwf_batch_create": ([_vp, _i, _i, ctypes.POINTER(_vp)], _i),
@@ -255,6 +256,10 @@ class Solver:
                               _stream(stream))
         _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
         return x, [s.as_dict() for s in stats]
+
+    def reserve(self, nrhs, inner, stream=None):
+        """Allocate the workspaces of a solve of nrhs right-hand sides now."""
+        _check(lib().odwf_solver_reserve(self._h, int(nrhs), int(inner), _stream(stream)))
 
     def close(self):
         if self._h:

@@ -135,6 +135,14 @@ class Server:
         budget = hbm_budget if hbm_budget is not None else float("inf")
         self.admission = Admission({n: max_slots for n in lattices}, per_slot, budget)
 
+    def close(self):
+        """Release every engine, solver and resident lattice."""
+        for e in self.engines.values():
+            e["batch"].close()
+            e["sol"].close()
+            e["lat"].close()
+        self.engines = {}
+
     def _admit(self, req: Request, now: float):
         from . import synth
         e = self.engines[req.lattice]

@@ -90,3 +90,42 @@ def test_committed_bench_line_keeps_the_contract():
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in cb, k
     assert cb["kind"] == "oracle" and cb["cores"] >= 1
+
+
+def _bench_args(argv):
+    """Parse bench.py's arguments without running it."""
+    import argparse
+    import bench
+    ns = argparse.Namespace(steps=20, warmup=5, time_budget=480.0, no_mixed_solve=False, no_hop_micro=False,
+                            no_cpu_baseline=False, no_fp64_compare=False, no_serving=False)
+    it = iter(argv)
+    for a in it:
+        key = a.lstrip("-").replace("-", "_")
+        if key in ("steps", "warmup"):
+            setattr(ns, key, int(next(it)))
+        elif key == "time_budget":
+            ns.time_budget = float(next(it))
+    return bench, ns
+
+
+def test_bench_plan_fits_the_driver_limit():
+    """The driver's command (--steps 20 --warmup 5, killed at 600 s) plans to
+    finish inside 400 s with the committed per-leg estimates, even after a slow
+    first import of torch (90 s), and every leg of the default run is planned."""
+    bench, ns = _bench_args(["--steps", "20", "--warmup", "5"])
+    legs = bench.plan(ns, elapsed0=0.0)
+    assert all(run for _, _, _, run in legs), legs
+    assert legs[-1][2] <= 400.0, legs
+    slow = bench.plan(ns, elapsed0=90.0)
+    assert max(end for _, _, end, run in slow if run) <= ns.time_budget < 600.0
+    # required legs run even when nothing else fits
+    tight = bench.plan(_bench_args(["--time-budget", "10"])[1])
+    assert [leg for leg, _, _, run in tight if run] == ["setup", "steps"]
+
+
+def test_bench_budget_skips_a_leg_that_would_overrun():
+    """Optional legs whose estimate would end past the budget are not started."""
+    bench, ns = _bench_args(["--time-budget", "200"])
+    legs = {leg: run for leg, _, _, run in bench.plan(ns)}
+    assert legs["mixed_solve"] and legs["hop_micro"]
+    assert not legs["fp64_solve"]
