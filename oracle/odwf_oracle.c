@@ -37,7 +37,7 @@
  *   - §2 (conjugate gradient): the solve is textbook Hestenes-Stiefel CG on
  *     the Hermitian positive-definite normal operator S_e^dag S_e.
  *
- * Mutation testing: building with -DORACLE_PLANT=k (k = 1..9) plants one
+ * Mutation testing: building with -DORACLE_PLANT=k (k = 1..12) plants one
  * deliberate, plausible mistake (see PLANT below) so that the tests can show
  * that their pins reject it; the normal build never defines it.
  *
@@ -521,9 +521,20 @@ static void op_schur_normal(const ctx_t* c, const cplx* in, cplx* out) {
 static int apply_op(const ctx_t* c, int op, const cplx* in, cplx* out) {
   long n = c->n5;
   switch (op) {
-    case OR_OP_HOP_EO: hop5(c, 0, in, out, 0, 1); return 0;
-    case OR_OP_HOP_OE: hop5(c, 0, in, out, 1, 0); return 0;
-    case OR_OP_M5INV: apply_m5(&c->g, c->Ns, c->Ainv, in, out, -1); return 0;
+    case OR_OP_HOP_EO: hop5(c, 0, in, out, PLANT(10) ? 1 : 0, PLANT(10) ? 0 : 1); return 0;
+    case OR_OP_HOP_OE: hop5(c, 0, in, out, PLANT(10) ? 0 : 1, PLANT(10) ? 1 : 0); return 0;
+    case OR_OP_M5INV:
+      if (PLANT(12)) { /* the transposed matrix */
+        int m = 4 * c->Ns;
+        cplx* T = malloc(sizeof(cplx) * m * m);
+        for (int i = 0; i < m; i++)
+          for (int j = 0; j < m; j++) T[i * m + j] = c->Ainv[j * m + i];
+        apply_m5(&c->g, c->Ns, T, in, out, -1);
+        free(T);
+        return 0;
+      }
+      apply_m5(&c->g, c->Ns, c->Ainv, in, out, -1);
+      return 0;
     case OR_OP_D: op_D(c, in, out); return 0;
     case OR_OP_DDAG: op_Ddag(c, in, out); return 0;
     case OR_OP_DDAGD: {
@@ -705,7 +716,7 @@ double oracle_normal_residual(const int dims[4], int bc_t, const cplx* U, int Ns
   mask_parity(&c.g, c.Ns, fe, 1);
   mask_parity(&c.g, c.Ns, ye, 1);
   op_schur_normal(&c, ye, t);
-  for (long i = 0; i < n; i++) t[i] = fe[i] - t[i];
+  for (long i = 0; i < n; i++) t[i] = PLANT(11) ? fe[i] + t[i] : fe[i] - t[i];
   double r = sqrt(vnorm2(n, t) / vnorm2(n, fe));
   free(fe); free(ye); free(t);
   ctx_free(&c);

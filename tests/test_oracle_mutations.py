@@ -12,6 +12,9 @@ Planted mistakes:
   7 Schur complement 1 + A^-1 W_eo A^-1 W_oe instead of 1 - ...
   8 hop normalised by -1 instead of -1/2
   9 z hop taken in the opposite direction
+ 10 even-odd hop entries with output and input parities exchanged
+ 11 normal-system residual formed as f + N y
+ 12 site-local A^{-1} applied transposed
 
 Exchanging the chiral projectors of L_+ and L_- is not among them: that gives
 R5 D R5 (R5: s -> Ns + 1 - s), the same operator up to relabelling s when
@@ -25,7 +28,8 @@ from oracle import build, oracle
 
 PLANTS = {1: "projector sign", 2: "missing link adjoint", 3: "boundary factor dropped",
           4: "boundary-term sign", 5: "one shift direction for both chiralities", 6: "Wilson mass 5 - m0",
-          7: "Schur sign", 8: "hop normalisation", 9: "z hop reversed"}
+          7: "Schur sign", 8: "hop normalisation", 9: "z hop reversed", 10: "hop parities swapped",
+          11: "normal residual sign", 12: "A^-1 transposed"}
 
 # every pin, with the arguments its parametrisation uses
 PIN_CALLS = [
@@ -41,6 +45,9 @@ PIN_CALLS = [
     (pins.test_m5_inverse_and_structure, {}),
     (pins.test_eo_solve_matches_dense_inverse, {"bc_t": -1}),
     (pins.test_eo_normal_solve_matches_dense, {}),
+    (pins.test_hop_entries_are_parity_blocks_of_dense_wilson, {"dims": (4, 2, 2, 6), "bc_t": -1}),
+    (pins.test_m5inv_entry_is_the_site_local_inverse, {}),
+    (pins.test_normal_residual_against_dense_schur_from_pinned_blocks, {"bc_t": -1}),
 ]
 
 

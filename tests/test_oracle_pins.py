@@ -251,3 +251,98 @@ def test_cg_iteration_count_bounded_by_dimension():
     b = synth.make_source(dims, 4, 1, 1000)[0]
     _, it, rr, _ = oracle.solve(U, b, M0, w, 0.5 / (2 * M0), oracle.SOLVE_FULL, tol=1e-10)
     assert 0 < it <= 8 * 4 * 12 and rr <= 1e-10
+
+
+def _parity_split(dims):
+    """Boolean masks (even, odd) over the rows of a dense 4D operator, basis
+    [t][z][y][x][spin][colour]."""
+    X, Y, Z, T = dims
+    ev = np.repeat(oracle.parity_mask((T, Z, Y, X)).reshape(-1), 12)
+    return ev, ~ev
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 2, 2, 6)], ids=["2^4", "4x2x2x6"])
+@pytest.mark.parametrize("bc_t", [1, -1])
+def test_hop_entries_are_parity_blocks_of_dense_wilson(dims, bc_t):
+    """The even-odd hop entries of the oracle equal, slice by slice, the
+    parity blocks of the pinned 4D Wilson matrix with its diagonal removed,
+    W = D_w - (4 - m0) (the hopping term of D_w, §2 with H = H_w):
+    HOP_EO gives W_eo psi_o on even sites and zeros on odd ones, HOP_OE gives
+    W_oe psi_e on odd sites.  The input's other parity must not contribute."""
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    Ns = 4
+    U = synth.make_gauge(dims, 0.6, 23)
+    W = dense_dw(U, M0, bc_t) - (4 - M0) * np.eye(V * 12)
+    ev, od = _parity_split(dims)
+    rng = np.random.default_rng(41)
+    psi = _rand5(rng, Ns, dims)
+    w = omega_zolotarev(LMIN, LMAX, Ns)
+    for op, rows, cols in ((oracle.OP_HOP_EO, ev, od), (oracle.OP_HOP_OE, od, ev)):
+        out = oracle.apply(op, U, psi, M0, w, 0.01, bc_t).reshape(Ns, V * 12)
+        blk = np.zeros_like(W)
+        blk[np.ix_(rows, cols)] = W[np.ix_(rows, cols)]
+        expect = psi.reshape(Ns, V * 12) @ blk.T
+        assert np.abs(out - expect).max() < 1e-13
+        assert np.all(out[:, ~rows] == 0)
+    # the off-parity blocks of W vanish: W couples only opposite parities
+    assert np.abs(W[np.ix_(ev, ev)]).max() == 0 and np.abs(W[np.ix_(od, od)]).max() == 0
+
+
+def test_m5inv_entry_is_the_site_local_inverse():
+    """M5INV applies A^{-1} (A = (4 - m0) + omega^{-1}(1 - L)(1 + L)^{-1}) at
+    every site: the (s, spin) matrix of the oracle's m5_matrix, which the
+    factorisation D = omega (A + W)(1 + L) pins, acting on each site's
+    Ns x 4 x 3 block, and its product with A is the identity."""
+    dims = (2, 2, 2, 4)
+    Ns = 8
+    U = synth.make_gauge(dims, 0.5, 5)
+    w = omega_zolotarev(LMIN, LMAX, Ns)
+    mu = 0.04 / (2 * M0)
+    rng = np.random.default_rng(6)
+    psi = _rand5(rng, Ns, dims)
+    Ai = oracle.m5_matrix(Ns, M0, w, mu, oracle.M5_AINV)
+    A = oracle.m5_matrix(Ns, M0, w, mu, oracle.M5_A)
+    out = oracle.apply(oracle.OP_M5INV, U, psi, M0, w, mu)
+    # psi[s][site][spin][colour] -> per site a (s, spin) vector for each colour
+    v = np.moveaxis(psi.reshape(Ns, -1, 4, 3), 0, 1).reshape(-1, Ns * 4, 3)
+    expect = np.moveaxis((Ai @ v).reshape(-1, Ns, 4, 3), 1, 0).reshape(psi.shape)
+    assert np.abs(out - expect).max() < 1e-13
+    back = np.moveaxis((A @ np.moveaxis(out.reshape(Ns, -1, 4, 3), 0, 1).reshape(-1, Ns * 4, 3))
+                       .reshape(-1, Ns, 4, 3), 1, 0).reshape(psi.shape)
+    assert np.abs(back - psi).max() < 1e-12
+
+
+@pytest.mark.parametrize("bc_t", [1, -1])
+def test_normal_residual_against_dense_schur_from_pinned_blocks(bc_t):
+    """oracle_normal_residual(f, y) = |f_e - S_e^dag S_e y_e| / |f_e| with the
+    even-site Schur complement S_e = 1 - A^{-1} W_eo A^{-1} W_oe built here
+    densely from the pinned pieces (parity blocks of the dense Wilson matrix,
+    the site-local A^{-1}), not from the oracle's Schur entries."""
+    dims = (2, 2, 2, 2)
+    X, Y, Z, T = dims
+    V = 16
+    Ns = 4
+    U = synth.make_gauge(dims, 0.5, 13)
+    w = omega_zolotarev(LMIN, LMAX, Ns)
+    mu = 0.05 / (2 * M0)
+    W = np.kron(np.eye(Ns), dense_dw(U, M0, bc_t) - (4 - M0) * np.eye(V * 12))
+    Ainv = m5_full(oracle.m5_matrix(Ns, M0, w, mu, oracle.M5_AINV), V)
+    ev4, od4 = _parity_split(dims)
+    ev, od = np.tile(ev4, Ns), np.tile(od4, Ns)
+    Weo, Woe = W[np.ix_(ev, od)], W[np.ix_(od, ev)]
+    Ae, Ao = Ainv[np.ix_(ev, ev)], Ainv[np.ix_(od, od)]
+    Se = np.eye(ev.sum()) - Ae @ Weo @ Ao @ Woe
+    N = Se.conj().T @ Se
+    rng = np.random.default_rng(19)
+    f, y = _rand5(rng, Ns, dims), _rand5(rng, Ns, dims)
+    fe, ye = f.reshape(-1)[ev], y.reshape(-1)[ev]
+    # a y close to the solution, so the residual is small and a sign error is large
+    ysol = np.linalg.solve(N, fe)
+    ynear = y.reshape(-1).copy()
+    ynear[ev] = ysol + 1e-6 * ye
+    for yy in (y.reshape(-1), ynear):
+        expect = np.linalg.norm(fe - N @ yy[ev]) / np.linalg.norm(fe)
+        got = oracle.normal_residual(U, f, yy.reshape(f.shape), M0, w, mu, bc_t)
+        # rounding of N y (entries of order |f|) bounds the difference, not its size
+        assert abs(got - expect) <= 1e-12, (got, expect)
