@@ -156,6 +156,24 @@ void odwf_solver_destroy(odwf_solver s);
 odwf_status odwf_apply(odwf_solver s, odwf_op op, const double* mq, odwf_prec prec, int nrhs,
                        const void* in, void* out, void* stream);
 
+/* Bytes of the per-device scratch array behind odwf_apply_noalloc. */
+#define ODWF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* odwf_apply without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operators, arguments, results and errors as odwf_apply; the
+ * packed half fields it works in are carved from a file-scope device array of
+ * ODWF_NOALLOC_SCRATCH_BYTES per GPU (held from the first lattice created on
+ * that GPU until the process ends) instead of the solver's workspace.  A call
+ * whose operator needs more scratch than that for one launch's right-hand
+ * sides (at most 256 / Ns) returns ODWF_ENOMEM with the sizes in
+ * odwf_last_error() and queues nothing.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads, other
+ * solvers) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero.  No profiling events are recorded. */
+odwf_status odwf_apply_noalloc(odwf_solver s, odwf_op op, const double* mq, odwf_prec prec,
+                               int nrhs, const void* in, void* out, void* stream);
+
 /* Solve for nrhs right-hand sides (independent masses mq[r] and tolerances
  * tol[r], host arrays).  inner = ODWF_FP64: plain FP64 CG; ODWF_FP32: FP32 CG
  * with FP64 reliable updates; ODWF_FP16S / ODWF_BF16S: FP64 defect correction

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -16,6 +17,8 @@
 using namespace odwf;
 
 namespace odwf {
+hipError_t noalloc_init(int device);
+void* noalloc_scratch(int device);
 const char* last_error_cstr();
 void prof_enable(int on);
 void prof_read(long long* launches, double* ms, double* bytes);
@@ -58,6 +61,9 @@ extern "C" odwf_status odwf_lattice_create(const int dims[4], int bc_t, int devi
   HIPCHK(hipGetDeviceCount(&ndev));
   REQUIRE(device >= 0 && device < ndev, "odwf_lattice_create: bad device index");
   HIPCHK(hipSetDevice(device));
+  // set-up of the device: the address of the allocation-free entry point's
+  // scratch array on this device (once per device)
+  HIPCHK(noalloc_init(device));
   odwf_lattice L = new odwf_lattice_s();
   for (int d = 0; d < 4; d++) {
     L->dims[d] = dims[d];
@@ -201,9 +207,26 @@ extern "C" void odwf_solver_destroy(odwf_solver S) {
 // operator application
 // ------------------------------------------------------------------------------
 
+// the half fields each operator uses, as bits: input even (1), input odd (2),
+// output even (4), output odd (8), even scratch (16), odd scratch (32)
+static int apply_needs(odwf_op op) {
+  const bool full = op == ODWF_OP_D || op == ODWF_OP_DDAG || op == ODWF_OP_DDAGD;
+  int m = 0;
+  if (op != ODWF_OP_HOP_EO) m |= 1;
+  if (op != ODWF_OP_HOP_OE && op < ODWF_OP_SCHUR) m |= 2;
+  if (op != ODWF_OP_HOP_OE) m |= 4;
+  if (op == ODWF_OP_HOP_OE || op == ODWF_OP_M5INV || full) m |= 8;
+  if (full || op == ODWF_OP_SCHUR_DAG || op == ODWF_OP_SCHUR_NORMAL) m |= 16;
+  if (full || op >= ODWF_OP_SCHUR) m |= 32;
+  return m;
+}
+
+// supplies the half field named `name` (nrhs right-hand sides, precision prec)
+using HalfFn = std::function<HV(const char* name, int nrhs, int prec)>;
+
 static odwf_status apply_chunk(odwf_solver S, odwf_op op, const double* mq, int prec, int r0,
-                               int nrhs, const void* in, void* out, hipStream_t st) {
-  Workspace& W = S->workspace(st);
+                               int nrhs, const void* in, void* out, hipStream_t st,
+                               const HalfFn& get, bool noprof) {
   const Geom& g = S->lat->g;
   const int Ns = S->Ns;
   OpCtx c;
@@ -211,16 +234,12 @@ static odwf_status apply_chunk(odwf_solver S, odwf_op op, const double* mq, int 
   c.st = st;
   c.prec = prec;
   c.nrhs = nrhs;
+  c.noprof = noprof;
   for (int r = 0; r < MAXRHS; r++) c.kappa[r] = r < nrhs ? -mq[r0 + r] / (2.0 * S->m0) : 0.0;
-  // the half fields each operator uses: inputs (even, odd), outputs, scratch
-  const bool full = op == ODWF_OP_D || op == ODWF_OP_DDAG || op == ODWF_OP_DDAGD;
-  const bool need_ie = op != ODWF_OP_HOP_EO, need_io = op != ODWF_OP_HOP_OE && op < ODWF_OP_SCHUR;
-  const bool need_oe = op != ODWF_OP_HOP_OE, need_oo = op == ODWF_OP_HOP_OE || op == ODWF_OP_M5INV || full;
-  const bool need_te = full || op == ODWF_OP_SCHUR_DAG || op == ODWF_OP_SCHUR_NORMAL;
-  const bool need_to = full || op >= ODWF_OP_SCHUR;
-  auto half = [&](bool need, const char* name) {
-    return need ? W.half(name, g.h, nrhs, Ns, prec) : HV();
-  };
+  const int needs = apply_needs(op);
+  const bool need_ie = needs & 1, need_io = needs & 2, need_oe = needs & 4, need_oo = needs & 8;
+  const bool need_te = needs & 16, need_to = needs & 32;
+  auto half = [&](bool need, const char* name) { return need ? get(name, nrhs, prec) : HV(); };
   HV ie = half(need_ie, "ap.ie"), io = half(need_io, "ap.io");
   HV oe = half(need_oe, "ap.oe"), oo = half(need_oo, "ap.oo");
   HV te = half(need_te, "ap.te"), to = half(need_to, "ap.to");
@@ -292,10 +311,73 @@ extern "C" odwf_status odwf_apply(odwf_solver S, odwf_op op, const double* mq, o
   HIPCHK(hipSetDevice(S->lat->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(S->mtx);
+  Workspace& W = S->workspace(st);
+  const long h = S->lat->g.h;
+  const int Ns = S->Ns;
+  const HalfFn get = [&](const char* name, int n, int p) { return W.half(name, h, n, Ns, p); };
   const int chunk = max_rhs_per_launch(S->Ns);
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {
     const int n = std::min(chunk, nrhs - r0);
-    odwf_status s = apply_chunk(S, op, mq, (int)prec, r0, n, in, out, st);
+    odwf_status s = apply_chunk(S, op, mq, (int)prec, r0, n, in, out, st, get, false);
+    if (s != ODWF_OK) return s;
+  }
+  return ODWF_OK;
+}
+
+// bytes of one half field in the scratch array, rounded up to 256 bytes
+static size_t scratch_half_bytes(long h, int nrhs, int Ns, int prec) {
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return up(half_bytes(h, nrhs, Ns, prec)) + up(scale_bytes(h, nrhs, Ns, prec));
+}
+
+extern "C" odwf_status odwf_apply_noalloc(odwf_solver S, odwf_op op, const double* mq,
+                                          odwf_prec prec, int nrhs, const void* in, void* out,
+                                          void* stream) {
+  REQUIRE(S && mq && in && out, "odwf_apply_noalloc: null argument");
+  REQUIRE(nrhs >= 1, "odwf_apply_noalloc: nrhs must be >= 1");
+  REQUIRE(in != out, "odwf_apply_noalloc: in and out must be distinct buffers");
+  REQUIRE(prec >= ODWF_FP64 && prec <= ODWF_BF16S, "odwf_apply_noalloc: bad precision");
+  REQUIRE(op >= ODWF_OP_HOP_EO && op <= ODWF_OP_SCHUR_NORMAL, "odwf_apply_noalloc: unknown operator");
+  REQUIRE(S->lat->loaded, "odwf_apply_noalloc: gauge field not loaded");
+  for (int r = 0; r < nrhs; r++) REQUIRE(std::isfinite(mq[r]), "odwf_apply_noalloc: mq must be finite");
+  const long h = S->lat->g.h;
+  const int Ns = S->Ns;
+  const int chunk = max_rhs_per_launch(Ns);
+  const int n0 = std::min(chunk, nrhs);
+  const int needs = apply_needs(op);
+  int nhalves = 0;
+  for (int b = 0; b < 6; b++) nhalves += (needs >> b) & 1;
+  const size_t need = (size_t)nhalves * scratch_half_bytes(h, n0, Ns, (int)prec);
+  if (need > ODWF_NOALLOC_SCRATCH_BYTES) {
+    set_error("odwf_apply_noalloc: this operator needs " + std::to_string(need) +
+              " bytes of scratch for " + std::to_string(n0) +
+              " right-hand side(s) per launch; the maximum is " +
+              std::to_string((size_t)ODWF_NOALLOC_SCRATCH_BYTES));
+    return ODWF_ENOMEM;
+  }
+  HIPCHK(hipSetDevice(S->lat->device));
+  unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(S->lat->device));
+  REQUIRE(base, "odwf_apply_noalloc: no scratch address for this device");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  size_t off = 0;
+  // half fields carved one after another from the scratch array (every
+  // element is written by a pack or an operator kernel before it is read, so
+  // nothing has to start at zero)
+  const HalfFn get = [&](const char*, int n, int p) {
+    HV v;
+    v.prec = p;
+    v.d = base + off;
+    const size_t db = (half_bytes(h, n, Ns, p) + 255) & ~size_t(255);
+    const size_t sb = (scale_bytes(h, n, Ns, p) + 255) & ~size_t(255);
+    v.sc = sb ? reinterpret_cast<float*>(base + off + db) : nullptr;
+    off += db + sb;
+    return v;
+  };
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int n = std::min(chunk, nrhs - r0);
+    off = 0;
+    odwf_status s = apply_chunk(S, op, mq, (int)prec, r0, n, in, out, st, get, true);
     if (s != ODWF_OK) return s;
   }
   return ODWF_OK;

@@ -180,7 +180,7 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   // launches gated to the active right-hand sides of a batch are counted with
   // the bytes of all nrhs (exact while every slot is active); launches gated to
   // pending reliable updates mostly exit at once and are not counted
-  const bool prof = prof_on() && (!o.gate || o.gate_mode == GATE_ACTIVE);
+  const bool prof = prof_on() && !c.noprof && (!o.gate || o.gate_mode == GATE_ACTIVE);
   if (prof) prof_begin(c.st, (c.prec & 3) * 2 + (dag ? 1 : 0));
   hipError_t e = launch_hop(a, c.prec, c.S->Ns, c.st);
   if (prof) {

@@ -93,6 +93,7 @@ struct OpCtx {
   int prec;  // storage precision of the half fields passed to the helpers
   int nrhs;
   double kappa[MAXRHS];
+  bool noprof = false;  // never record profiling events (the allocation-free path)
   const void* coef() const { return prec == PREC64 ? S->coef64 : S->coef32; }
   const void* links(int par) const { return prec == PREC64 ? S->lat->U64[par] : S->lat->U32[par]; }
   long h() const { return S->lat->g.h; }

@@ -57,6 +57,7 @@ SYMBOLS = {
     "odwf_solver_create": ([_vp, _i, _d, _dp, ctypes.POINTER(_vp)], _i),
     "odwf_solver_destroy": ([_vp], None),
     "odwf_apply": ([_vp, _i, _dp, _i, _i, _vp, _vp, _vp], _i),
+    "odwf_apply_noalloc": ([_vp, _i, _dp, _i, _i, _vp, _vp, _vp], _i),
     "odwf_solve": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_solver_reserve": ([_vp, _i, _i, _vp], _i),
     "odwf_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
@@ -238,6 +239,20 @@ class Solver:
         mqa, mqp = _f64arr(np.broadcast_to(np.asarray(mq, np.float64), (nrhs,)))
         _check(lib().odwf_apply(self._h, int(op), mqp, int(prec), nrhs, _dev_ptr(psi, "in"),
                                 _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def apply_noalloc(self, op, psi, mq, prec=FP64, out=None, stream=None):
+        """odwf_apply_noalloc: the same operator with no device allocation in the
+        call (`out`, when not given, is allocated here by torch beforehand)."""
+        import torch
+        nrhs = psi.shape[0]
+        if tuple(psi.shape) != self.spinor_shape(nrhs):
+            raise ValueError("spinor has the wrong shape")
+        if out is None:
+            out = torch.empty_like(psi)
+        mqa, mqp = _f64arr(np.broadcast_to(np.asarray(mq, np.float64), (nrhs,)))
+        _check(lib().odwf_apply_noalloc(self._h, int(op), mqp, int(prec), nrhs, _dev_ptr(psi, "in"),
+                                        _dev_ptr(out, "out"), _stream(stream)))
         return out
 
     def solve(self, b, mq, tol=1e-10, mode=SOLVE_FULL, inner=FP64, maxiter=100000, x=None,
