@@ -245,13 +245,12 @@ static hipError_t batch_iteration(odwf_batch B, hipStream_t st) {
   HV* xacc = B->inner == PREC64 ? &B->y : &B->x;
   HopOpt k4;
   k4.cg_r = &B->r;
-  k4.cg_x = xacc;
-  k4.cg_p = &B->p;
   k4.scal = B->dscal;
   k4.partial = B->partial;
   HIPRET(apply_normal(cin, B->p, B->t, B->v, B->v, B->partial, &k4, B->dscal, GATE_ACTIVE));
   HIPRET(launch_fin(FIN_BETA, B->partial, nbh, k, B->dscal, nullptr, st));
-  HIPRET(launch_vec_xpby(B->inner, B->r.d, B->r.sc, B->p.d, B->p.sc, B->dscal, h, k, Ns, st));
+  HIPRET(launch_vec_cg_step(B->inner, B->r.d, B->r.sc, B->p.d, B->p.sc, xacc->d, xacc->sc, B->dscal, h, k,
+                            Ns, st));
   // gated update: y += x_s, x_s = 0, r = f - N y (FP64), true |r|^2
   if (B->inner != PREC64) {
     HIPRET(launch_vec_convert(B->inner, B->x.d, B->x.sc, PREC64, B->y.d, nullptr, 1, h, k, Ns, st,

@@ -63,22 +63,38 @@ __global__ void vec_convert_kernel(const void* src, const float* src_sc, void* d
   }
 }
 
+// CG vector step after the scalars of the iteration are known:
+//   x += alpha p   (for every right-hand side that iterated: alpha != 0, which
+//                   includes one that converged at this iteration's beta)
+//   p  = r + beta p (for the right-hand sides still active)
 template <class P>
-__global__ void vec_xpby_kernel(const void* x, const float* x_sc, void* y, float* y_sc,
-                                const CGScal* scal, long h, int nrhs, int Ns) {
+__global__ void vec_cg_step_kernel(const void* r_, const float* r_sc, void* p_, float* p_sc, void* x_,
+                                   float* x_sc, const CGScal* scal, long h, int nrhs, int Ns) {
   using R = typename P::real;
   const int inner = nrhs * Ns;
   const int spb = blockDim.x / inner;
   const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
-  if (!scal[r].active) return;
-  const R beta = (R)scal[r].beta;
+  const bool act = scal[r].active != 0;
+  const double alpha = scal[r].alpha;
+  if (!act && alpha == 0.0) return;
+  const R al = (R)alpha, beta = (R)scal[r].beta;
   for (long j = (long)blockIdx.x * spb + sl; j < h; j += (long)gridDim.x * spb) {
-    cpx<R> a[12], b[12];
-    load_site<P>(x, x_sc, j, r, s, nrhs, Ns, a);
-    load_site<P>(y, y_sc, j, r, s, nrhs, Ns, b);
+    cpx<R> pv[12];
+    load_site<P>(p_, p_sc, j, r, s, nrhs, Ns, pv);
+    if (alpha != 0.0) {
+      cpx<R> xv[12];
+      load_site<P>(x_, x_sc, j, r, s, nrhs, Ns, xv);
 #pragma unroll
-    for (int c = 0; c < 12; c++) b[c] = cadd(a[c], cscale(beta, b[c]));
-    store_site<P>(y, y_sc, j, r, s, nrhs, Ns, b);
+      for (int c = 0; c < 12; c++) xv[c] = cadd(xv[c], cscale(al, pv[c]));
+      store_site<P>(x_, x_sc, j, r, s, nrhs, Ns, xv);
+    }
+    if (act) {
+      cpx<R> rv[12];
+      load_site<P>(r_, r_sc, j, r, s, nrhs, Ns, rv);
+#pragma unroll
+      for (int c = 0; c < 12; c++) pv[c] = cadd(rv[c], cscale(beta, pv[c]));
+      store_site<P>(p_, p_sc, j, r, s, nrhs, Ns, pv);
+    }
   }
 }
 
@@ -86,7 +102,7 @@ template <class P>
 __global__ void vec_norm2_kernel(const void* v, const float* sc, double* partial, long h, int nrhs,
                                  int Ns) {
   using R = typename P::real;
-  __shared__ double red[1024 + 16 * MAXRHS];
+  __shared__ double red[1024];
   const int inner = nrhs * Ns;
   const int spb = blockDim.x / inner;
   const int sl = threadIdx.x / inner, lr = threadIdx.x % inner, r = lr / Ns, s = lr % Ns;
@@ -98,9 +114,7 @@ __global__ void vec_norm2_kernel(const void* v, const float* sc, double* partial
 #pragma unroll
       for (int c = 0; c < 12; c++) acc += (double)cnorm2(a[c]);
     }
-  red[threadIdx.x] = acc;
-  block_reduce_rhs(
-      red, blockDim.x, nrhs, [&](int k) { return (k % inner) / Ns; }, red + 1024, partial, blockIdx.x);
+  block_reduce_rhs(sl < spb ? acc : 0.0, Ns, spb, nrhs, red, partial, blockIdx.x);
 }
 
 #define ODWF_PREC_SWITCH(prec, KERNEL, ...)                                             \
@@ -148,11 +162,12 @@ hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_vec_xpby(int prec, const void* x, const float* x_sc, void* y, float* y_sc,
-                           const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st) {
+hipError_t launch_vec_cg_step(int prec, const void* r, const float* r_sc, void* p, float* p_sc, void* x,
+                              float* x_sc, const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st) {
   const int block = vec_spb(nrhs, Ns) * nrhs * Ns;
   const dim3 gr(vec_nblocks(h, nrhs, Ns));
-  ODWF_PREC_SWITCH(prec, vec_xpby_kernel, gr, dim3(block), 0, st, x, x_sc, y, y_sc, scal, h, nrhs, Ns);
+  ODWF_PREC_SWITCH(prec, vec_cg_step_kernel, gr, dim3(block), 0, st, r, r_sc, p, p_sc, x, x_sc, scal, h, nrhs,
+                   Ns);
   return hipGetLastError();
 }
 
@@ -224,20 +239,30 @@ hipError_t launch_vec_copy_rhs(int prec_src, const void* src, const float* src_s
 // ---------------------------------------------------------------------------
 __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrhs, CGScal* scal,
                            double* out, int gated) {
-  __shared__ double red[256];
+  // all right-hand sides in one pass: thread t adds the partials of blocks
+  // t, t + 256, ... per right-hand side, then one fixed tree over the threads
+  __shared__ double red[MAXRHS * 256];
   __shared__ double sums[MAXRHS];
-  for (int r = 0; r < nrhs; r++) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partial[(long)b * nrhs + r];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+  double acc[MAXRHS];
+#pragma unroll
+  for (int r = 0; r < MAXRHS; r++) acc[r] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < MAXRHS; r++)
+      if (r < nrhs) acc[r] += partial[(long)b * nrhs + r];
+  }
+#pragma unroll
+  for (int r = 0; r < MAXRHS; r++)
+    if (r < nrhs) red[r * 256 + threadIdx.x] = acc[r];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int r = 0; r < nrhs; r++) red[r * 256 + threadIdx.x] += red[r * 256 + threadIdx.x + w];
     }
-    if (threadIdx.x == 0) sums[r] = red[0];
     __syncthreads();
   }
+  if ((int)threadIdx.x < nrhs) sums[threadIdx.x] = red[threadIdx.x * 256];
+  __syncthreads();
   if ((int)threadIdx.x >= nrhs) return;
   const int r = threadIdx.x;
   const double v = sums[r];
@@ -320,21 +345,28 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
 // partials of blocks [b * 1024, (b + 1) * 1024) per right-hand side in a fixed
 // tree and writes them to dst[b * nrhs + r]
 __global__ void partial_reduce_kernel(const double* partial, int nblocks, int nrhs, double* dst) {
-  __shared__ double red[256];
+  __shared__ double red[MAXRHS * 256];
   const int b0 = blockIdx.x * 1024;
   const int b1 = min(b0 + 1024, nblocks);
-  for (int r = 0; r < nrhs; r++) {
-    double acc = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) acc += partial[(long)b * nrhs + r];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+  double acc[MAXRHS];
+#pragma unroll
+  for (int r = 0; r < MAXRHS; r++) acc[r] = 0.0;
+  for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < MAXRHS; r++)
+      if (r < nrhs) acc[r] += partial[(long)b * nrhs + r];
+  }
+#pragma unroll
+  for (int r = 0; r < MAXRHS; r++)
+    if (r < nrhs) red[r * 256 + threadIdx.x] = acc[r];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int r = 0; r < nrhs; r++) red[r * 256 + threadIdx.x] += red[r * 256 + threadIdx.x + w];
     }
-    if (threadIdx.x == 0) dst[(long)blockIdx.x * nrhs + r] = red[0];
     __syncthreads();
   }
+  if ((int)threadIdx.x < nrhs) dst[(long)blockIdx.x * nrhs + threadIdx.x] = red[threadIdx.x * 256];
 }
 
 size_t partial_bytes(int nblocks, int nrhs) {

@@ -246,7 +246,14 @@ __device__ __forceinline__ void load_site_cached_raw(const void* base, const flo
   else sc = typename P::real(1);
 }
 
-template <class P>
+// NT = 1: nontemporal stores (written once, not re-read by this launch)
+#ifndef ODWF_NT_STORE
+#define ODWF_NT_STORE 0
+#endif
+#ifndef ODWF_NT_LINKS
+#define ODWF_NT_LINKS 0
+#endif
+template <class P, int NT = 0>
 __device__ __forceinline__ void store_site(void* base, float* scale, long j, int r, int s, int nrhs,
                                            int Ns, const cpx<typename P::real> (&v)[12]) {
   using R = typename P::real;
@@ -258,11 +265,21 @@ __device__ __forceinline__ void store_site(void* base, float* scale, long j, int
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; c++) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    scale[(j * nrhs + r) * Ns + s] = m;
+    if constexpr (NT) __builtin_nontemporal_store(m, scale + (j * nrhs + r) * Ns + s);
+    else scale[(j * nrhs + r) * Ns + s] = m;
     inv = m > 0.f ? 1.0f / m : 0.f;
   }
 #pragma unroll
-  for (int cg = 0; cg < NCG; cg++) b[off + cg * Ns] = pack_chunk<P>(&v[cg * P::CPB], inv);
+  for (int cg = 0; cg < NCG; cg++) {
+    const uint4 q = pack_chunk<P>(&v[cg * P::CPB], inv);
+    if constexpr (NT) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 w = {q.x, q.y, q.z, q.w};
+      __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(b + off + cg * Ns));
+    } else {
+      b[off + cg * Ns] = q;
+    }
+  }
 }
 
 // is right-hand side r selected by the gate?
@@ -611,27 +628,28 @@ __device__ __forceinline__ void column_pass_lds(cpx<R>* buf, int nsb, int nrhs, 
 }
 
 // ---------------------------------------------------------------------------
-// deterministic per-right-hand-side block reduction
-// vals[k] (k < count) in LDS, key(k) gives the right-hand side of entry k.
-// Writes partial[slot * nrhs + r].  All threads must call.
+// deterministic per-right-hand-side block reduction of one double per lane.
+// Lanes are laid out (site slot sl, right-hand side r, slice s) with s fastest,
+// tid = (sl * nrhs + r) * Ns + s (Ns a power of two dividing 64, so the Ns
+// lanes of one (site, r) lie in one wave).  Those Ns lanes add their values by
+// a fixed xor butterfly of cross-lane moves (no LDS traffic; every lane ends
+// with the same bits, each pairwise addition being commutative); lane s = 0
+// puts the sum in tmp[sl * nrhs + r]; one lane per right-hand side then adds
+// the nsl site sums in site order and writes partial[slot * nrhs + r].
+// All threads of the block call it; padded threads (g >= nsl * nrhs) pass 0.
+// tmp: LDS of at least nsl * nrhs doubles.
 // ---------------------------------------------------------------------------
-template <class KeyF>
-__device__ void block_reduce_rhs(double* vals, int count, int nrhs, KeyF key, double* tmp,
-                                 double* partial, long slot) {
-  __syncthreads();
+__device__ __forceinline__ void block_reduce_rhs(double v, int Ns, int nsl, int nrhs, double* tmp,
+                                                 double* partial, long slot) {
+  for (int m = Ns >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, Ns);
   const int tid = threadIdx.x;
-  if (tid < nrhs * 16) {
-    const int r = tid / 16, q = tid % 16;
-    double acc = 0.0;
-    for (int k = q; k < count; k += 16)
-      if (key(k) == r) acc += vals[k];
-    tmp[tid] = acc;
-  }
+  const int g = tid / Ns;
+  __syncthreads();  // tmp may alias LDS the block used before
+  if ((tid & (Ns - 1)) == 0 && g < nsl * nrhs) tmp[g] = v;
   __syncthreads();
   if (tid < nrhs) {
     double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; q++) acc += tmp[tid * 16 + q];
+    for (int k = 0; k < nsl; k++) acc += tmp[k * nrhs + tid];
     partial[slot * nrhs + tid] = acc;
   }
 }

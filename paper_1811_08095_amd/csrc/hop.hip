@@ -9,7 +9,8 @@
 // multiplied by bc_t, then
 //     y = c_h * P_h(W psi) + c_x * P_x(x_site),   out = P_o(y)
 // where P_h, P_x, P_o are fifth-dimension programs (A^{-1}, A^{-dag}, A^dag, ...
-// as products of cyclic bidiagonal factors), and optionally a fused CG step.
+// as products of cyclic bidiagonal factors), and optionally the fused CG
+// residual step r -= alpha y with its |r|^2 partial sums.
 //
 // Thread layout: a block holds spb sites of the output parity; each site has
 // nrhs * Ns lanes (s fastest) that read consecutive 16-byte chunks of every
@@ -65,7 +66,17 @@ __device__ __forceinline__ void stage_links(const void* links, long j0, int nsb,
   } else {
     const float4* src = reinterpret_cast<const float4*>(links) + j0 * 8 * 3;
     for (int m = threadIdx.x; m < nmat; m += blockDim.x) {
+#if ODWF_NT_LINKS
+      // links are read once per launch: keep them from displacing spinor rows in L2
+      typedef float f32x4 __attribute__((ext_vector_type(4)));
+      const f32x4* sv = reinterpret_cast<const f32x4*>(src + m * 3);
+      const f32x4 av = __builtin_nontemporal_load(sv), bv = __builtin_nontemporal_load(sv + 1),
+                  cv = __builtin_nontemporal_load(sv + 2);
+      float4 a = make_float4(av.x, av.y, av.z, av.w), b = make_float4(bv.x, bv.y, bv.z, bv.w),
+             c = make_float4(cv.x, cv.y, cv.z, cv.w);
+#else
       float4 a = src[m * 3 + 0], b = src[m * 3 + 1], c = src[m * 3 + 2];
+#endif
       cpx<float> u[6] = {{a.x, a.y}, {a.z, a.w}, {b.x, b.y}, {b.z, b.w}, {c.x, c.y}, {c.z, c.w}};
       cpx<R>* d = lnk + m * 9;
 #pragma unroll
@@ -349,17 +360,11 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
         }
         store_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
       }
-      {  // x += alpha p
-        cpx<R> xx[12], pv[12];
-        load_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
-        load_site<P>(a.cg_p, a.cg_p_sc, j, r, s, nrhs, NS, pv);
-#pragma unroll
-        for (int c = 0; c < 12; c++) xx[c] = cadd(xx[c], cscale(al, pv[c]));
-        store_site<P>(a.cg_x, a.cg_x_sc, j, r, s, nrhs, NS, xx);
-      }
+      // x += alpha p runs in the vector step after beta (vec_cg_step_kernel),
+      // which reads p there anyway
     }
   } else if (valid && a.out) {
-    store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+    store_site<P, ODWF_NT_STORE>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
   }
 
   return nval;
@@ -367,10 +372,17 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
 
 // minimum waves per SIMD the register allocation must allow (the fused FP32
 // kernels fit four when their column programs run across lanes)
+#ifndef ODWF_HOP_WAVES32
+#define ODWF_HOP_WAVES32 4
+#endif
+#ifndef ODWF_HOP_WAVES64
+#define ODWF_HOP_WAVES64 2
+#endif
 template <class P, int NS, bool PLAIN>
 struct HopWaves {
-  static constexpr int W =
-      sizeof(typename P::real) == 8 ? 2 : ((PLAIN || LanePass<typename P::real, NS>::on) ? 4 : 2);
+  static constexpr int W = sizeof(typename P::real) == 8
+                               ? ODWF_HOP_WAVES64
+                               : ((PLAIN || LanePass<typename P::real, NS>::on) ? ODWF_HOP_WAVES32 : 2);
 };
 
 template <class P, int NS, bool DAG, bool PLAIN>
@@ -402,7 +414,6 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   R* kap = reinterpret_cast<R*>(smem + region);
   double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
-  double* rtmp = red + blockDim.x;
   const R* coef = reinterpret_cast<const R*>(a.coef);
   if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
   stage_links<P>(a.links, j0, nsb, lnk);
@@ -511,7 +522,7 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
     for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
   }
   if constexpr (PLAIN) {
-    if (valid) store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+    if (valid) store_site<P, ODWF_NT_STORE>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
     return;
   }
 
@@ -522,11 +533,7 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   asm volatile("" : "+v"(slr));
   const double nval = fused_tail<P, NS>(a, acc, valid, j0 + slr, sl, r, s, nsb, buf, coef, kap,
                                         x_first ? X_LDS : X_LOAD);
-  if (a.partial) {
-    red[tid] = valid ? nval : 0.0;
-    block_reduce_rhs(
-        red, blockDim.x, nrhs, [&](int k) { return (k % inner) / NS; }, rtmp, a.partial, blockIdx.x);
-  }
+  if (a.partial) block_reduce_rhs(valid ? nval : 0.0, NS, a.spb, nrhs, red, a.partial, blockIdx.x);
 }
 
 
@@ -615,7 +622,6 @@ __global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kern
   const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   R* kap = reinterpret_cast<R*>(smem + region);
   double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
-  double* rtmp = red + blockDim.x;
   const R* coef = reinterpret_cast<const R*>(a.coef);
   if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
 
@@ -738,9 +744,7 @@ __global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kern
   if (!PLAIN && a.partial) {
     // one slot for the whole sweep, zeros in the slots of the other steps so
     // that the partial array has the layout of the one-t-per-block kernel
-    red[tid] = valid ? nval : 0.0;
-    block_reduce_rhs(
-        red, blockDim.x, nrhs, [&](int k) { return (k % inner) / NS; }, rtmp, a.partial, blockIdx.x);
+    block_reduce_rhs(valid ? nval : 0.0, NS, spb, nrhs, red, a.partial, blockIdx.x);
     if (tid < nrhs) {
       for (int k = 1; k < a.sweep; k++)
         a.partial[((long)gridDim.x + (long)blockIdx.x * (a.sweep - 1) + (k - 1)) * nrhs + tid] = 0.0;
@@ -748,6 +752,13 @@ __global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kern
   }
 }
 
+// extra LDS per block (plain / fused kernels): caps the blocks resident per CU
+#ifndef ODWF_HOP_SMEM_PAD
+#define ODWF_HOP_SMEM_PAD 0
+#endif
+#ifndef ODWF_HOP_SMEM_PAD_F
+#define ODWF_HOP_SMEM_PAD_F 0
+#endif
 template <class P, int NS>
 static size_t hop_smem(int spb, int nrhs, int block, bool plain, bool sweep) {
   using R = typename P::real;
@@ -757,7 +768,8 @@ static size_t hop_smem(int spb, int nrhs, int block, bool plain, bool sweep) {
   const size_t buf_n = sweep ? (xch_n > col_n ? xch_n : col_n) : col_n;
   const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   size_t off = (region + MAXRHS * sizeof(R) + 15) & ~size_t(15);
-  return off + (size_t)(block + 16 * MAXRHS) * sizeof(double);
+  return off + (size_t)(block + 16 * MAXRHS) * sizeof(double) +
+         (plain ? ODWF_HOP_SMEM_PAD : ODWF_HOP_SMEM_PAD_F);
 }
 
 template <class P, int NS>

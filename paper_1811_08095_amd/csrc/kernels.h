@@ -50,9 +50,10 @@ hipError_t launch_vec_convert(int prec_src, const void* src, const float* src_sc
 hipError_t launch_vec_copy_rhs(int prec_src, const void* src, const float* src_sc, int nrhs_src,
                                int r_src, int prec_dst, void* dst, float* dst_sc, int nrhs_dst,
                                int r_dst, long h, int Ns, hipStream_t st);
-// y = x + beta_r y for active right-hand sides
-hipError_t launch_vec_xpby(int prec, const void* x, const float* x_sc, void* y, float* y_sc,
-                           const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st);
+// CG vector step: x += alpha_r p for right-hand sides that iterated (alpha != 0),
+// then p = r + beta_r p for the active ones
+hipError_t launch_vec_cg_step(int prec, const void* r, const float* r_sc, void* p, float* p_sc, void* x,
+                              float* x_sc, const CGScal* scal, long h, int nrhs, int Ns, hipStream_t st);
 // per-block partial sums of |v|^2 per right-hand side
 hipError_t launch_vec_norm2(int prec, const void* v, const float* sc, double* partial, long h,
                             int nrhs, int Ns, int* nblocks_out, hipStream_t st);

@@ -86,11 +86,10 @@ struct HopArgs {
   float* out_sc;
   const void* xin;      // same-parity input for the x term
   const float* xin_sc;
-  // fused CG update (CG mode 2): r -= alpha out, x += alpha p, |r|^2
+  // fused CG residual update (CG mode 2): r -= alpha out, |r|^2; cg_p is the
+  // right-hand side f of a residual f - out (CG mode 3)
   void* cg_r;
   float* cg_r_sc;
-  void* cg_x;
-  float* cg_x_sc;
   const void* cg_p;
   const float* cg_p_sc;
   const CGScal* scal;

@@ -155,8 +155,6 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   a.xin_sc = o.x ? o.x->sc : nullptr;
   a.cg_r = o.cg_r ? o.cg_r->d : nullptr;
   a.cg_r_sc = o.cg_r ? o.cg_r->sc : nullptr;
-  a.cg_x = o.cg_x ? o.cg_x->d : nullptr;
-  a.cg_x_sc = o.cg_x ? o.cg_x->sc : nullptr;
   a.cg_p = o.cg_p ? o.cg_p->d : nullptr;
   a.cg_p_sc = o.cg_p ? o.cg_p->sc : nullptr;
   a.scal = o.scal;
@@ -186,7 +184,7 @@ hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out
   if (prof) {
     const double n5 = (double)L->g.h * c.nrhs * c.S->Ns;
     int streams = 1 + (out ? 1 : 0) + (o.x ? 1 : 0);
-    if (o.cg_r) streams += 5;          // r, x, p read; r, x written
+    if (o.cg_r) streams += 2;          // r read and written
     else if (o.cg_p) streams += 1;     // f read
     const double link_b = (double)L->g.h * 8 * (c.prec == PREC64 ? 18 * 8 : 12 * 4);
     prof_end(c.st, n5 * site_bytes(c.prec) * streams + link_b);

@@ -107,8 +107,7 @@ struct HopOpt {
   // CG fusion
   double* partial = nullptr;
   HV* cg_r = nullptr;
-  HV* cg_x = nullptr;
-  const HV* cg_p = nullptr;  // p (mode 2) or f (mode 3)
+  const HV* cg_p = nullptr;  // f of the residual f - N p (mode 3)
   const CGScal* scal = nullptr;
   // gating (GateMode): only right-hand sides selected by gate do any work
   const CGScal* gate = nullptr;

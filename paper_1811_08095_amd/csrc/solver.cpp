@@ -315,13 +315,11 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       for (;;) {
         HopOpt k4;
         k4.cg_r = &r;
-        k4.cg_x = &e1;
-        k4.cg_p = &p;
         k4.scal = dscal;
         k4.partial = partial;
         CHK(apply_normal(c64, p, o0, e2, e2, partial, &k4));
         CHK(launch_fin(FIN_BETA, partial, nbh, nrhs, dscal, nullptr, st));
-        CHK(launch_vec_xpby(PREC64, r.d, nullptr, p.d, nullptr, dscal, h, nrhs, Ns, st));
+        CHK(launch_vec_cg_step(PREC64, r.d, nullptr, p.d, nullptr, e1.d, nullptr, dscal, h, nrhs, Ns, st));
         CHK(poll.push(dscal, nrhs, st));
         const CGScal* v = poll.view(2);
         if (v && !any(v, 0)) break;
@@ -344,13 +342,11 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       for (;;) {
         HopOpt k4;
         k4.cg_r = &rr;
-        k4.cg_x = &xs;
-        k4.cg_p = &p;
         k4.scal = dscal;
         k4.partial = partial;
         CHK(apply_normal(cin, p, t, v, v, partial, &k4));
         CHK(launch_fin(FIN_BETA, partial, nbh, nrhs, dscal, nullptr, st));
-        CHK(launch_vec_xpby(inner, rr.d, rr.sc, p.d, p.sc, dscal, h, nrhs, Ns, st));
+        CHK(launch_vec_cg_step(inner, rr.d, rr.sc, p.d, p.sc, xs.d, xs.sc, dscal, h, nrhs, Ns, st));
         CHK(poll.push(dscal, nrhs, st));
         const CGScal* vw = poll.view(2);
         if (vw && (!any(vw, 0) || any(vw, 1))) break;
@@ -392,13 +388,11 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       for (;;) {
         HopOpt k4;
         k4.cg_r = &rr;
-        k4.cg_x = &xs;
-        k4.cg_p = &p;
         k4.scal = dscal;
         k4.partial = partial;
         CHK(apply_normal(cin, p, t, v, v, partial, &k4));
         CHK(launch_fin(FIN_BETA, partial, nbh, nrhs, dscal, nullptr, st));
-        CHK(launch_vec_xpby(inner, rr.d, rr.sc, p.d, p.sc, dscal, h, nrhs, Ns, st));
+        CHK(launch_vec_cg_step(inner, rr.d, rr.sc, p.d, p.sc, xs.d, xs.sc, dscal, h, nrhs, Ns, st));
         CHK(poll.push(dscal, nrhs, st));
         const CGScal* vw = poll.view(2);
         if (vw && !any(vw, 0)) break;

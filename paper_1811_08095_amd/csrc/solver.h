@@ -21,7 +21,7 @@ hipError_t apply_schur_dag(const OpCtx& c, const HV& in, const HV& te, const HV&
 //   K2: v = A^{-dag} (p - A^{-1} W_eo t), partial |S_e p|^2 (if partial_u)
 //   K3: t = A^{-dag} W^dag_oe v
 //   K4: out = A^dag v - W^dag_eo t
-// With k4 options the last step can instead update r, x (CG step) or write a
+// With k4 options the last step can instead update r (r -= alpha N p, |r|^2) or write a
 // residual f - N p.
 hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, const HV& out,
                         double* partial_u, const HopOpt* k4 = nullptr, const CGScal* gate = nullptr,

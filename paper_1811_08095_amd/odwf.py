@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libodwf.so")
+# ODWF_LIB selects another build of the library (tuning builds); default in-tree
+LIBPATH = os.environ.get("ODWF_LIB") or os.path.join(HERE, "libodwf.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENAN, EBUSY = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
