@@ -112,12 +112,15 @@ typedef enum { ODWF_SOLVE_EO_NORMAL = 0, ODWF_SOLVE_FULL = 1 } odwf_mode;
 
 typedef struct {
   int iters;             /* CG iterations (inner iterations for mixed solves)          */
-  int reliable_updates;  /* FP64 true-residual recomputations inside the inner solve  */
-  int outer_steps;       /* FP64 defect-correction steps (FP16S/BF16S inner)           */
+  int reliable_updates;  /* FP32 inner: FP64 true-residual updates of this right-hand
+                            side's own iterate, the final confirmation included; else 0 */
+  int outer_steps;       /* FP16S/BF16S inner: FP64 defect-correction steps this
+                            right-hand side took part in; else 0                       */
   int status;            /* odwf_status of this right-hand side                        */
   double true_rel_resid; /* |f - S_e^dag S_e y| / |f|, recomputed in FP64 at the end   */
   double full_rel_resid; /* FULL mode: |b - D x| / |b| in FP64; -1 in EO_NORMAL mode   */
-  double seconds;        /* wall time of the whole call                                */
+  double seconds;        /* wall time from the call's start until this right-hand side
+                            was seen finished (the whole call for the last one)        */
 } odwf_stats;
 
 /* ---- lattices and gauge fields ----------------------------------------- */
@@ -185,6 +188,35 @@ odwf_status odwf_apply_noalloc(odwf_solver s, odwf_op op, const double* mq, odwf
 odwf_status odwf_solve(odwf_solver s, odwf_mode mode, const double* mq, const double* tol,
                        int nrhs, odwf_prec inner, int maxiter, const void* b, void* x,
                        int use_x0, odwf_stats* stats, void* stream);
+
+/* Multi-mass solves for one source (paper §2: the fermion forces of the HMC
+ * need the solution of the even-odd normal system at several quark masses for
+ * one pseudofermion field -- the Hasenbusch masses, m_ud, m_s, m_c, and the
+ * Pauli-Villars mass 2 m0 of Eq. (1)-(2)):
+ *     S_e(m_k)^dag S_e(m_k) y_k = b_e,   k = 0 .. nmass - 1,
+ * all masses iterated together in multi-right-hand-side CG launches, so that
+ * every link load serves all of them (per mass: own mu = mq[k] / (2 m0), own
+ * tolerance tol[k], own CG scalars).  1 <= nmass <= 256 / Ns (and <= 16).
+ * b: ONE canonical device field (its even sites are the source of every mass;
+ * its odd sites are not read).  y: caller-owned device array in the packed
+ * even-half FP64 layout of the library (nothing canonical is allocated, so
+ * several masses fit where canonical outputs would not):
+ *     complex128 y[((j * nmass + k) * 12 + c) * Ns + s],
+ *     j = ((t * Lz + z) * Ly + y) * (Lx / 2) + x / 2 over the even sites
+ *         (x + y + z + t even), c = spin * 3 + colour, s = 0 .. Ns - 1,
+ * i.e. nmass * (V / 2) * Ns * 12 complex128.  With use_y0 != 0, y holds the
+ * initial guesses on entry.  per_launch = masses iterated together in one
+ * multi-right-hand-side CG (1 .. nmass), or 0 to let the library choose: all
+ * of them together while one right-hand side's FP32 half field fits the
+ * 256 MB memory-side cache, one at a time above that (where the wider sites of
+ * a shared launch cost more neighbour re-fetch than its shared links save).
+ * inner, maxiter, stats, stream and the return codes as for odwf_solve (mode
+ * EO_NORMAL); the workspaces are those of an odwf_solve of per_launch
+ * right-hand sides (plus one packed field of per_launch masses when
+ * per_launch < nmass). */
+odwf_status odwf_solve_masses(odwf_solver s, const double* mq, const double* tol, int nmass,
+                              odwf_prec inner, int maxiter, const void* b, void* y, int use_y0,
+                              int per_launch, odwf_stats* stats, void* stream);
 
 /* Allocate now the workspaces odwf_solve uses on `stream` for nrhs right-hand
  * sides (at most one launch's worth, 256 / Ns, is held) in precision `inner`,

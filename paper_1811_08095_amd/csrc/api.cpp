@@ -416,6 +416,70 @@ extern "C" odwf_status odwf_solve(odwf_solver S, odwf_mode mode, const double* m
   return worst;
 }
 
+// A single right-hand side's FP32 half field above this size does not stay in
+// the memory-side cache (256 MB): multi-right-hand-side launches then lose
+// more in neighbour re-fetch (their sites are nmass times larger) than they
+// save in shared link reads, and the masses are solved one launch each
+// (measured at 64^3 x 8 x 16 with six masses: shared launches 0.85x, at 32^4
+// 0.91x, at 16^4 1.05x the speed of one mass at a time).
+constexpr size_t MASSES_SHARED_MAX_HALF_BYTES = size_t(256) << 20;
+
+extern "C" odwf_status odwf_solve_masses(odwf_solver S, const double* mq, const double* tol,
+                                         int nmass, odwf_prec inner, int maxiter, const void* b,
+                                         void* y, int use_y0, int per_launch, odwf_stats* stats,
+                                         void* stream) {
+  REQUIRE(S && mq && tol && b && y, "odwf_solve_masses: null argument");
+  REQUIRE(nmass >= 1 && nmass <= max_rhs_per_launch(S->Ns),
+          "odwf_solve_masses: nmass must be in [1, min(16, 256 / Ns)]");
+  REQUIRE(per_launch >= 0 && per_launch <= nmass, "odwf_solve_masses: per_launch must be in [0, nmass]");
+  REQUIRE(inner >= ODWF_FP64 && inner <= ODWF_BF16S, "odwf_solve_masses: bad inner precision");
+  REQUIRE(maxiter >= 1, "odwf_solve_masses: maxiter must be >= 1");
+  REQUIRE(b != y, "odwf_solve_masses: b and y must be distinct buffers");
+  REQUIRE(S->lat->loaded, "odwf_solve_masses: gauge field not loaded");
+  for (int k = 0; k < nmass; k++) {
+    REQUIRE(std::isfinite(mq[k]), "odwf_solve_masses: mq must be finite");
+    REQUIRE(tol[k] > 0 && tol[k] < 1, "odwf_solve_masses: tol must be in (0, 1)");
+  }
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  const long h = S->lat->g.h;
+  const int Ns = S->Ns;
+  if (per_launch == 0)
+    per_launch = half_bytes(h, 1, Ns, PREC32) > MASSES_SHARED_MAX_HALF_BYTES ? 1 : nmass;
+  SolveIO io;
+  io.bcast_b = true;
+  if (per_launch == nmass) {  // every mass in the same launches, straight into y
+    io.y_packed = y;
+    return solve_chunk(S, ODWF_SOLVE_EO_NORMAL, mq, tol, 0, nmass, (int)inner, maxiter, b, nullptr,
+                       use_y0, stats, st, io);
+  }
+  // groups of per_launch masses, each solved in a packed field of its own and
+  // copied into its slots of y
+  Workspace& W = S->workspace(st);
+  HV yg = W.half("m.y", h, per_launch, Ns, PREC64);
+  if (!yg.d) {
+    set_error("odwf_solve_masses: out of device memory for workspaces");
+    return ODWF_ENOMEM;
+  }
+  io.y_packed = yg.d;
+  odwf_status worst = ODWF_OK;
+  for (int k0 = 0; k0 < nmass; k0 += per_launch) {
+    const int n = std::min(per_launch, nmass - k0);
+    if (use_y0)
+      for (int q = 0; q < n; q++)
+        HIPCHK(launch_vec_copy_rhs(PREC64, y, nullptr, nmass, k0 + q, PREC64, yg.d, nullptr, n, q, h, Ns, st));
+    odwf_status sc = solve_chunk(S, ODWF_SOLVE_EO_NORMAL, mq + k0, tol + k0, 0, n, (int)inner, maxiter, b,
+                                 nullptr, use_y0, stats ? stats + k0 : nullptr, st, io);
+    if (sc == ODWF_EHIP || sc == ODWF_ENOMEM || sc == ODWF_EINVAL) return sc;
+    if (sc != ODWF_OK && worst == ODWF_OK) worst = sc;
+    for (int q = 0; q < n; q++)
+      HIPCHK(launch_vec_copy_rhs(PREC64, yg.d, nullptr, n, q, PREC64, y, nullptr, nmass, k0 + q, h, Ns, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return worst;
+}
+
 extern "C" odwf_status odwf_solver_reserve(odwf_solver S, int nrhs, odwf_prec inner, void* stream) {
   REQUIRE(S, "odwf_solver_reserve: null solver");
   REQUIRE(nrhs >= 1, "odwf_solver_reserve: nrhs must be >= 1");

@@ -323,7 +323,10 @@ __global__ void fin_kernel(int kind, const double* partial, int nblocks, int nrh
       c.rr = v;
       c.rmax2 = v;
       c.update = 0;
-      c.nupd += 1;
+      if (c.iters > c.upd_iters) {  // an update of this right-hand side's own iterate
+        c.nupd += 1;
+        c.upd_iters = c.iters;
+      }
       if (!finite) {
         c.nan = 1;
         c.active = 0;

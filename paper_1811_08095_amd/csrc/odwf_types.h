@@ -67,7 +67,8 @@ struct CGScal {
   int iters;      // iterations done
   int maxiter;    // iteration cap
   int confirm;    // 1: iterated convergence or maxiter requests a true-residual update
-  int nupd;       // true-residual (reliable) updates done
+  int nupd;       // true-residual (reliable) updates this right-hand side iterated into
+  int upd_iters;  // iteration count at its last true-residual update
 };
 
 // which right-hand sides a gated kernel works on

@@ -166,16 +166,16 @@ size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner) {
   return b;
 }
 
-bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B) {
+bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B, bool own_y) {
   B.e0 = W.half("s.e0", h, nrhs, Ns, PREC64);  // f
-  B.e1 = W.half("s.e1", h, nrhs, Ns, PREC64);  // y
+  if (own_y) B.e1 = W.half("s.e1", h, nrhs, Ns, PREC64);  // y (else the caller's packed field)
   B.e2 = W.half("s.e2", h, nrhs, Ns, PREC64);  // FP64 even scratch / residual
   B.o0 = W.half("s.o0", h, nrhs, Ns, PREC64);  // FP64 odd scratch
   const int nbmax = std::max(hop_nblocks((int)h, nrhs, Ns), vec_nblocks(h, nrhs, Ns));
   B.partial = (double*)W.get("s.partial", partial_bytes(nbmax, nrhs));
   B.scal = (CGScal*)W.get("s.scal", 2 * MAXRHS * sizeof(CGScal));
   B.res = (double*)W.get("s.res", 4 * MAXRHS * sizeof(double));
-  bool ok = B.e0.d && B.e1.d && B.e2.d && B.o0.d && B.partial && B.scal && B.res;
+  bool ok = B.e0.d && (B.e1.d || !own_y) && B.e2.d && B.o0.d && B.partial && B.scal && B.res;
   if (inner == PREC64) {
     B.r = W.half("s.r64", h, nrhs, Ns, PREC64);
     B.p = W.half("s.p64", h, nrhs, Ns, PREC64);
@@ -203,7 +203,7 @@ static hipError_t true_residual(const OpCtx& c64, const HV& f, const HV& y, cons
 
 odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double* tol, int r0,
                         int nrhs, int inner, int maxiter, const void* b, void* x, int use_x0,
-                        odwf_stats* stats, hipStream_t st) {
+                        odwf_stats* stats, hipStream_t st, const SolveIO& io) {
   const auto t0 = std::chrono::steady_clock::now();
   Workspace& W = S->workspace(st);
   const Geom& g = S->lat->g;
@@ -228,9 +228,14 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
   } while (0)
 
   SolveBufs B;
-  if (!solve_buffers(W, h, nrhs, Ns, inner, B)) {
+  if (!solve_buffers(W, h, nrhs, Ns, inner, B, io.y_packed == nullptr)) {
     set_error("odwf_solve: out of device memory for workspaces");
     return ODWF_ENOMEM;
+  }
+  if (io.y_packed) {  // the caller's packed even half is the CG iterate itself
+    B.e1.d = io.y_packed;
+    B.e1.sc = nullptr;
+    B.e1.prec = PREC64;
   }
   HV e0 = B.e0, e1 = B.e1, e2 = B.e2, o0 = B.o0;
   double* partial = B.partial;
@@ -261,9 +266,21 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       CHK(launch_vec_zero(PREC64, e1.d, nullptr, h, nrhs, Ns, st));
     }
   } else {
-    CHK(launch_pack_spinor(PREC64, b, r0, e0.d, nullptr, 0, nrhs, Ns, g, st));
-    if (use_x0) CHK(launch_pack_spinor(PREC64, x, r0, e1.d, nullptr, 0, nrhs, Ns, g, st));
-    else CHK(launch_vec_zero(PREC64, e1.d, nullptr, h, nrhs, Ns, st));
+    if (io.bcast_b) {
+      // one source for every right-hand side of the chunk (several masses)
+      CHK(launch_pack_spinor(PREC64, b, 0, o0.d, nullptr, 0, 1, Ns, g, st));
+      for (int q = 0; q < nrhs; q++)
+        CHK(launch_vec_copy_rhs(PREC64, o0.d, nullptr, 1, 0, PREC64, e0.d, nullptr, nrhs, q, h, Ns, st));
+    } else {
+      CHK(launch_pack_spinor(PREC64, b, r0, e0.d, nullptr, 0, nrhs, Ns, g, st));
+    }
+    if (io.y_packed) {
+      if (!use_x0) CHK(launch_vec_zero(PREC64, e1.d, nullptr, h, nrhs, Ns, st));
+    } else if (use_x0) {
+      CHK(launch_pack_spinor(PREC64, x, r0, e1.d, nullptr, 0, nrhs, Ns, g, st));
+    } else {
+      CHK(launch_vec_zero(PREC64, e1.d, nullptr, h, nrhs, Ns, st));
+    }
   }
 
   // ---- device scalars --------------------------------------------------------
@@ -286,7 +303,14 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
   CHK(poll.init());
   CGScal cur[MAXRHS];
   int reliable = 0, outer = 0;
-  std::vector<int> inner_iters(nrhs, 0);
+  std::vector<int> inner_iters(nrhs, 0), outer_q(nrhs, 0);
+  // per right-hand side: seconds from the call's start until it was first seen finished
+  std::vector<double> t_done(nrhs, -1.0);
+  auto mark_done = [&]() {
+    const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int q = 0; q < nrhs; q++)
+      if (t_done[q] < 0 && !cur[q].active) t_done[q] = now;
+  };
 
   // initial true residual r = f - N y (or r = f from a zero guess)
   auto init_residual = [&](CGScal* sc) -> hipError_t {
@@ -328,6 +352,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       CHK(true_residual(c64, e0, e1, o0, e2, partial, dscal, dres));
       CHK(launch_vec_convert(PREC64, e2.d, nullptr, PREC64, r.d, nullptr, 0, h, nrhs, Ns, st));
       CHK(read_scal(dscal, cur, nrhs, st));
+      mark_done();
       reliable++;
     }
     for (int q = 0; q < nrhs; q++) inner_iters[q] = cur[q].iters;
@@ -357,6 +382,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       CHK(true_residual(c64, e0, e1, o0, e2, partial, dscal, dres));
       CHK(launch_vec_convert(PREC64, e2.d, nullptr, inner, rr.d, rr.sc, 0, h, nrhs, Ns, st));
       CHK(read_scal(dscal, cur, nrhs, st));
+      mark_done();
       reliable++;
     }
     for (int q = 0; q < nrhs; q++) inner_iters[q] = cur[q].iters;
@@ -367,6 +393,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     CHK(init_residual(dscal_out));
     CHK(read_scal(dscal_out, cur, nrhs, st));
     while (any(cur, 0)) {
+      for (int q = 0; q < nrhs; q++) outer_q[q] += cur[q].active ? 1 : 0;
       // inner system N e = r, started from e = 0
       CGScal hin[MAXRHS];
       for (int q = 0; q < nrhs; q++) {
@@ -407,6 +434,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
       CHK(hipMemcpyAsync(dscal_out, cur, nrhs * sizeof(CGScal), hipMemcpyHostToDevice, st));
       CHK(true_residual(c64, e0, e1, o0, e2, partial, dscal_out, dres));
       CHK(read_scal(dscal_out, cur, nrhs, st));
+      mark_done();
       for (int q = 0; q < nrhs; q++)
         if (fin[q].nan) cur[q].nan = 1, cur[q].active = 0;
     }
@@ -454,7 +482,7 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     CHK(m5(c64, o0, o0, prog_1pl_inv()));
     CHK(launch_unpack_spinor(PREC64, e1.d, nullptr, x, r0, 0, nrhs, Ns, g, st));
     CHK(launch_unpack_spinor(PREC64, o0.d, nullptr, x, r0, 1, nrhs, Ns, g, st));
-  } else {
+  } else if (!io.y_packed) {
     CHK(launch_unpack_spinor(PREC64, e1.d, nullptr, x, r0, 0, nrhs, Ns, g, st));
     CHK(launch_zero_canon_parity(x, r0, 1, nrhs, Ns, g, st));
   }
@@ -472,12 +500,13 @@ odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double*
     else if (stq == ODWF_ENOCONV && worst == ODWF_OK) worst = ODWF_ENOCONV;
     if (stats) {
       stats[q].iters = inner_iters[q];
-      stats[q].reliable_updates = inner == PREC64 ? 0 : reliable;
-      stats[q].outer_steps = outer;
+      // FP32: the FP64 true-residual updates of this right-hand side's own iterate
+      stats[q].reliable_updates = inner == PREC32 ? cur[q].nupd : 0;
+      stats[q].outer_steps = outer_q[q];
       stats[q].status = stq;
       stats[q].true_rel_resid = rel;
       stats[q].full_rel_resid = full_res[q];
-      stats[q].seconds = secs;
+      stats[q].seconds = t_done[q] >= 0 && t_done[q] < secs ? t_done[q] : secs;
     }
   }
   if (worst == ODWF_ENAN) set_error("odwf_solve: NaN/Inf in a residual norm");

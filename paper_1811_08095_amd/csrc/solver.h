@@ -27,9 +27,16 @@ hipError_t apply_normal(const OpCtx& c, const HV& p, const HV& t, const HV& v, c
                         double* partial_u, const HopOpt* k4 = nullptr, const CGScal* gate = nullptr,
                         int gate_mode = GATE_NONE);
 
+// how a solve chunk receives its source and returns its solution
+struct SolveIO {
+  bool bcast_b = false;      // b holds one right-hand side, the source of every one of the chunk
+  void* y_packed = nullptr;  // EO_NORMAL: caller's packed FP64 even half (nrhs right-hand sides),
+                             // used as the CG iterate and left holding the solution; x unused
+};
+
 odwf_status solve_chunk(odwf_solver S, int mode, const double* mq, const double* tol, int r0,
                         int nrhs, int inner, int maxiter, const void* b, void* x, int use_x0,
-                        odwf_stats* stats, hipStream_t st);
+                        odwf_stats* stats, hipStream_t st, const SolveIO& io = SolveIO());
 
 size_t solve_workspace_bytes(long h, int Ns, int nrhs, int inner);
 
@@ -42,6 +49,6 @@ struct SolveBufs {
   CGScal* scal = nullptr;
   double* res = nullptr;
 };
-bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B);
+bool solve_buffers(Workspace& W, long h, int nrhs, int Ns, int inner, SolveBufs& B, bool own_y = true);
 
 }  // namespace odwf

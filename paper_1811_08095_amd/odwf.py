@@ -61,6 +61,7 @@ SYMBOLS = {
     "odwf_apply_noalloc": ([_vp, _i, _dp, _i, _i, _vp, _vp, _vp], _i),
     "odwf_solve": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_solver_reserve": ([_vp, _i, _i, _vp], _i),
+    "odwf_solve_masses": ([_vp, _dp, _dp, _i, _i, _i, _vp, _vp, _i, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
     "odwf_zolotarev_omega": ([_i, _d, _d, _dp], _i),
     "odwf_batch_create": ([_vp, _i, _i, ctypes.POINTER(_vp)], _i),
@@ -272,6 +273,35 @@ class Solver:
                               _stream(stream))
         _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
         return x, [s.as_dict() for s in stats]
+
+    def packed_even_shape(self, nrhs):
+        """Shape of a packed even-half FP64 field of nrhs right-hand sides:
+        [V/2 even sites][nrhs][12 spin-colour][Ns] complex128."""
+        X, Y, Z, T = self.lattice.dims
+        return (X * Y * Z * T // 2, nrhs, 12, self.Ns)
+
+    def solve_masses(self, b, mq, tol=1e-10, inner=FP64, maxiter=100000, y=None, use_y0=False,
+                     per_launch=0, stream=None, raise_on_noconv=True):
+        """odwf_solve_masses: S_e(m_k)^dag S_e(m_k) y_k = b_e for every mass
+        m_k of `mq`, one source b [Ns][t][z][y][x][4][3] (or [1][...]);
+        per_launch masses per multi-right-hand-side CG (0: the library's choice);
+        returns (y packed [V/2][nmass][12][Ns] complex128, per-mass stats)."""
+        import torch
+        nm = len(mq)
+        if tuple(b.shape[-7:]) != self.spinor_shape(1)[1:]:
+            raise ValueError("source has the wrong shape")
+        if y is None:
+            y = torch.zeros(self.packed_even_shape(nm), dtype=torch.complex128, device=b.device)
+        elif tuple(y.shape) != self.packed_even_shape(nm):
+            raise ValueError("y has the wrong shape")
+        mqa, mqp = _f64arr(mq)
+        tla, tlp = _f64arr(np.broadcast_to(np.asarray(tol, np.float64), (nm,)))
+        stats = (Stats * nm)()
+        st = lib().odwf_solve_masses(self._h, mqp, tlp, nm, int(inner), int(maxiter), _dev_ptr(b, "b"),
+                                     _dev_ptr(y, "y"), 1 if use_y0 else 0, int(per_launch), stats,
+                                     _stream(stream))
+        _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
+        return y, [s.as_dict() for s in stats]
 
     def reserve(self, nrhs, inner, stream=None):
         """Allocate the workspaces of a solve of nrhs right-hand sides now."""
