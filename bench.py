@@ -300,7 +300,7 @@ def serving_leg(nreq, rate, inner="fp32"):
     reqs = serve.poisson_stream(nreq, rate, list(lattices))
     t0 = time.perf_counter()
     done = srv.run(reqs)
-    out = serve.summarize(done, time.perf_counter() - t0)
+    out = serve.summarize(done, time.perf_counter() - t0, srv.admission)
     out.update({"arrival_rate": rate, "lattices": list(lattices), "max_slots": 12, "inner": inner})
     srv.close()
     return out

@@ -264,6 +264,16 @@ odwf_status odwf_batch_retire(odwf_batch bt, int slot, void* x, odwf_stats* stat
 /* Slots currently free. */
 odwf_status odwf_batch_free_slots(odwf_batch bt, int* n);
 
+/* Device bytes odwf_batch_create allocates for an engine of max_slots slots
+ * on a lattice of extents dims (host computation; the resident lattice and
+ * solver excluded), so that a server can admit engines by HBM footprint
+ * before creating them. */
+odwf_status odwf_batch_footprint(const int dims[4], int Ns, int max_slots, odwf_prec inner,
+                                 size_t* bytes);
+
+/* Device bytes an existing engine holds (equal to its odwf_batch_footprint). */
+odwf_status odwf_batch_bytes(odwf_batch bt, size_t* bytes);
+
 void odwf_batch_destroy(odwf_batch bt);
 
 /* ---- profiling --------------------------------------------------------- */

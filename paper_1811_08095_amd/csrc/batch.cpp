@@ -77,6 +77,36 @@ static void kappas(odwf_batch B, double* kap) {
   for (int q = 0; q < MAXRHS; q++) kap[q] = q < B->k ? -B->mq[q] / (2.0 * B->S->m0) : 0.0;
 }
 
+// device bytes a batch engine allocates (the buffers of odwf_batch_create)
+static size_t batch_footprint_bytes(long h, int Ns, int k, int inner) {
+  auto buf = [](size_t b) { return b ? b : size_t(16); };
+  size_t t = 5 * buf(half_bytes(h, k, Ns, PREC64));  // f, y, e2, o0, bo
+  const int ninner = inner == PREC64 ? 4 : 5;       // p, r, t, v (+ x)
+  t += ninner * buf(half_bytes(h, k, Ns, inner));
+  if (k > 1) t += 5 * buf(half_bytes(h, 1, Ns, PREC64));  // admission / retirement scratch
+  const int nb = std::max(hop_nblocks((int)h, k, Ns), vec_nblocks(h, k, Ns));
+  t += partial_bytes(nb, k) + MAXRHS * sizeof(CGScal) + 4 * MAXRHS * sizeof(double);
+  return t;
+}
+
+extern "C" odwf_status odwf_batch_footprint(const int dims[4], int Ns, int max_slots, odwf_prec inner,
+                                            size_t* bytes) {
+  BREQ(dims && bytes, "odwf_batch_footprint: null argument");
+  BREQ(Ns == 4 || Ns == 8 || Ns == 16 || Ns == 32, "odwf_batch_footprint: unsupported Ns");
+  BREQ(max_slots >= 1 && max_slots <= max_rhs_per_launch(Ns), "odwf_batch_footprint: bad max_slots");
+  BREQ(inner == ODWF_FP64 || inner == ODWF_FP32, "odwf_batch_footprint: inner must be FP64 or FP32");
+  for (int d = 0; d < 4; d++) BREQ(dims[d] >= 2 && dims[d] % 2 == 0, "odwf_batch_footprint: bad extent");
+  const long h = (long)dims[0] * dims[1] * dims[2] * dims[3] / 2;
+  *bytes = batch_footprint_bytes(h, Ns, max_slots, (int)inner);
+  return ODWF_OK;
+}
+
+extern "C" odwf_status odwf_batch_bytes(odwf_batch B, size_t* bytes) {
+  BREQ(B && bytes, "odwf_batch_bytes: null argument");
+  *bytes = B->ws.total();
+  return ODWF_OK;
+}
+
 extern "C" odwf_status odwf_batch_create(odwf_solver S, int max_slots, odwf_prec inner,
                                          odwf_batch* out) {
   BREQ(S && out, "odwf_batch_create: null argument");

@@ -70,6 +70,8 @@ SYMBOLS = {
     "odwf_batch_poll": ([_vp, _i, _ip, ctypes.POINTER(Stats), _vp], _i),
     "odwf_batch_retire": ([_vp, _i, _vp, ctypes.POINTER(Stats), _vp], _i),
     "odwf_batch_free_slots": ([_vp, _ip], _i),
+    "odwf_batch_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
+    "odwf_batch_bytes": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _i),
     "odwf_batch_destroy": ([_vp], None),
     "odwf_profile_enable": ([_i], _i),
     "odwf_profile_read": ([ctypes.POINTER(ctypes.c_longlong), _dp, _dp], _i),
@@ -142,6 +144,13 @@ def zolotarev_omega(Ns, lmin=0.05, lmax=6.2):
 def footprint(dims, Ns, nrhs, inner):
     b = ctypes.c_size_t()
     _check(lib().odwf_footprint(_dims_arr(dims), int(Ns), int(nrhs), int(inner), ctypes.byref(b)))
+    return b.value
+
+
+def batch_footprint(dims, Ns, max_slots, inner):
+    """Device bytes of a batch engine of max_slots slots (odwf_batch_footprint)."""
+    b = ctypes.c_size_t()
+    _check(lib().odwf_batch_footprint(_dims_arr(dims), int(Ns), int(max_slots), int(inner), ctypes.byref(b)))
     return b.value
 
 
@@ -360,6 +369,12 @@ class Batch:
         n = ctypes.c_int()
         _check(lib().odwf_batch_free_slots(self._h, ctypes.byref(n)))
         return n.value
+
+    def nbytes(self):
+        """Device bytes the engine holds."""
+        b = ctypes.c_size_t()
+        _check(lib().odwf_batch_bytes(self._h, ctypes.byref(b)))
+        return b.value
 
     def close(self):
         if self._h:

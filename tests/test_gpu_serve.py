@@ -30,3 +30,51 @@ def test_serving_stream_small():
         for i in range(r.nrhs):
             Dx = oracle.apply(oracle.OP_D, U, x[i], 1.3, w, r.mq / 2.6)
             assert np.linalg.norm(b[i] - Dx) / np.linalg.norm(b[i]) < 1e3 * r.tol
+
+
+def test_memory_budget_defers_a_request_until_an_engine_is_evicted():
+    """A budget that holds one engine but not two: a request for the second
+    lattice waits while the first lattice's engine is busy, is admitted after
+    that engine drains and is evicted, and its result equals the same solve
+    done directly (and meets the oracle's residual)."""
+    import torch
+    from paper_1811_08095_amd import odwf
+    from paper_1811_08095_amd.serve import Request
+    lattices = {"A": {"dims": (4, 4, 4, 4), "Ns": 8, "eps": 0.5, "seed": 0},
+                "B": {"dims": (4, 4, 2, 4), "Ns": 8, "eps": 0.5, "seed": 2}}
+    fa = odwf.batch_footprint((4, 4, 4, 4), 8, 4, odwf.FP32)
+    fb = odwf.batch_footprint((4, 4, 2, 4), 8, 4, odwf.FP32)
+    srv = Server(lattices, max_slots=4, inner="fp32", iters_per_step=2, hbm_budget=max(fa, fb) * 1.2)
+    reqs = [Request(0, "A", 0.05, 3, 1e-10, 0.0, seed=101), Request(1, "B", 0.5, 2, 1e-10, 0.0, seed=102),
+            Request(2, "A", 0.04, 1, 1e-10, 0.0, seed=103)]
+    done = srv.run(reqs, time_limit=120, keep_solutions=True)
+    assert len(done) == 3
+    adm = srv.admission
+    print(f"deferred {adm.deferred_for_memory}, evictions {adm.evictions}, peak {adm.peak_bytes}, "
+          f"budget {adm.budget:.0f}, measured engine bytes {srv.engine_bytes_measured}")
+    assert adm.deferred_for_memory >= 1 and adm.evictions >= 1
+    assert adm.peak_bytes <= adm.budget
+    for name, nb in srv.engine_bytes_measured.items():
+        assert nb == adm.engine_bytes[name]  # the footprint the admission used is what was allocated
+    rb = next(r for r in done if r.lattice == "B")
+    assert rb.deferred and rb.admitted > 0
+    ra = [r for r in done if r.lattice == "A"]
+    assert rb.admitted >= max(r.finished for r in ra if r.rid == 0) - 1e-9
+    # the deferred request's result: the same system solved directly
+    spec = lattices["B"]
+    U = synth.make_gauge_device(spec["dims"], spec["eps"], spec["seed"])
+    lat = odwf.Lattice(spec["dims"], bc_t=-1)
+    lat.load_gauge(U)
+    sol = odwf.Solver(lat, 8, 1.3, odwf.zolotarev_omega(8, 0.05, 6.2))
+    b = synth.make_source_device(spec["dims"], 8, 2, rb.seed)
+    x, st = sol.solve(b, [0.5, 0.5], [1e-10, 1e-10], inner=odwf.FP32)
+    d = float(torch.linalg.vector_norm(x - rb.x) / torch.linalg.vector_norm(x))
+    assert d < 1e-7, d
+    w = sol.omega
+    Uh, bh, xh = U.cpu().numpy(), b.cpu().numpy(), rb.x.cpu().numpy()
+    for i in range(2):
+        Dx = oracle.apply(oracle.OP_D, Uh, xh[i], 1.3, w, 0.5 / 2.6)
+        assert np.linalg.norm(bh[i] - Dx) / np.linalg.norm(bh[i]) < 1e-7
+    sol.close()
+    lat.close()
+    srv.close()

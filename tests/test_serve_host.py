@@ -22,23 +22,47 @@ def test_poisson_stream_is_seeded_and_well_formed():
     assert len({r.seed for r in a}) == 400
 
 
-def test_admission_respects_slots_and_budget():
-    adm = Admission({"a": 12, "b": 12}, {"a": 10, "b": 100}, budget_bytes=1000)
-    r1 = Request(0, "a", 0.1, 12, 1e-8, 0.0)
-    r2 = Request(1, "a", 0.1, 1, 1e-8, 0.0)
-    r3 = Request(2, "b", 0.1, 9, 1e-8, 0.0)
-    r4 = Request(3, "b", 0.1, 2, 1e-8, 0.0)
-    assert adm.fits(r1)
-    adm.take(r1)
-    assert not adm.fits(r2)          # no free slot on engine a
-    adm2 = Admission({"a": 12, "b": 12}, {"a": 10, "b": 100}, budget_bytes=1000)
-    adm2.take(r1)
-    assert not adm2.fits(r3)         # 120 + 900 > 1000: over the HBM budget
-    assert adm2.fits(r4)
-    adm2.release(r1)
-    assert adm2.fits(r3) and adm2.in_flight == 0
+def test_admission_creates_engines_within_the_budget_and_evicts_idle_ones():
+    adm = Admission({"a": 400, "b": 700}, {"a": 12, "b": 12}, budget_bytes=1000)
+    ra1 = Request(0, "a", 0.1, 12, 1e-8, 0.0)
+    ra2 = Request(1, "a", 0.1, 1, 1e-8, 0.1)
+    rb = Request(2, "b", 0.1, 3, 1e-8, 0.2)
+    ra3 = Request(3, "a", 0.1, 1, 1e-8, 0.3)
+    # first request of a lattice: its engine is created (400 <= 1000)
+    assert adm.next_decision([ra1, ra2, rb, ra3]) == (ra1, "create", [])
+    adm.created("a")
+    adm.take(ra1)
+    # a's engine is full: ra2 waits for slots and holds back ra3 (FIFO per
+    # lattice); b's engine (700) does not fit beside a's (400) while a is busy
+    assert adm.decide(ra2) == ("wait_slots", [])
+    assert adm.decide(rb) == ("wait_memory", [])
+    assert adm.next_decision([ra2, rb, ra3]) == (None, None, rb)
+    # a finishes: ra2 goes into the live engine first (arrival order)
+    adm.release(ra1)
+    assert adm.next_decision([ra2, rb, ra3]) == (ra2, "admit", [])
+    adm.take(ra2)
+    # rb still does not fit, and holds back ra3 (so that a drains)
+    assert adm.next_decision([rb, ra3]) == (None, None, rb)
+    adm.release(ra2)
+    # a is idle: rb evicts it and creates b
+    assert adm.next_decision([rb, ra3]) == (rb, "create", ["a"])
+    adm.evicted("a")
+    adm.created("b")
+    adm.take(rb)
+    assert adm.live_bytes() == 700 and adm.evictions == 1 and adm.peak_bytes == 700
+    assert adm.decide(ra3) == ("wait_memory", [])
+
+
+def test_admission_rejects_what_can_never_fit():
+    adm = Admission({"a": 2000}, {"a": 4}, budget_bytes=1000)
+    with pytest.raises(ValueError):
+        adm.decide(Request(0, "a", 0.1, 1, 1e-8, 0.0))
+    adm2 = Admission({"a": 10}, {"a": 4}, budget_bytes=1000)
+    with pytest.raises(ValueError):
+        adm2.decide(Request(0, "a", 0.1, 5, 1e-8, 0.0))
+    adm2.created("a")
     with pytest.raises(AssertionError):
-        adm2.take(Request(4, "a", 0.1, 13, 1e-8, 0.0))
+        adm2.take(Request(1, "a", 0.1, 5, 1e-8, 0.0))
 
 
 def test_percentiles_and_summary():
