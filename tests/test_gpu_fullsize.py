@@ -94,14 +94,14 @@ def test_fullsize_reduced_precision_sampled(full, src, op, prec):
     assert 0 < err <= PREC_BOUND[prec]
 
 
-def test_fullsize_mixed_solve_sampled_residual(full, src):
-    """The benchmark's solve: FP32 inner CG with FP64 reliable updates,
-    m_q = 0.04, tolerance 1e-10, source seed 1005."""
+@pytest.fixture(scope="module")
+def solve_sites(full, src):
+    """Sampled sites for the solves' residuals and the links around them, kept
+    on the host: the canonical gauge field and the operator input leave the
+    device before the solves need the memory."""
     import torch
-    src.clear()  # the operator input is not needed here; the solve needs the memory
+    src.clear()
     sites = sampled.pick_sites(DIMS, 16, None, seed=7)
-    # links around the sampled sites, kept on the host: the canonical gauge
-    # field leaves the device before the solve needs the memory
     coords = np.concatenate([sampled.frame(s, DIMS, 1, -1)[0] for s in sites])
     lin = ((coords[:, 3] * DIMS[2] + coords[:, 2]) * DIMS[1] + coords[:, 1]) * DIMS[0] + coords[:, 0]
     uniq, first = np.unique(lin, return_index=True)
@@ -113,11 +113,20 @@ def test_fullsize_mixed_solve_sampled_residual(full, src):
     def gu(c):
         cl = ((c[:, 3] * DIMS[2] + c[:, 2]) * DIMS[1] + c[:, 1]) * DIMS[0] + c[:, 0]
         return U_host[np.searchsorted(uniq, cl)]
+    return sites, gu
 
+
+@pytest.mark.parametrize("mq", [0.0025, 0.04, 0.5], ids=["light", "strange", "charm"])
+def test_fullsize_mixed_solve_sampled_residual(full, solve_sites, mq):
+    """The benchmark's solve at the three masses of the full-size
+    configuration: FP32 inner CG with FP64 reliable updates, tolerance 1e-10,
+    source seed 1005; the oracle recomputes b - D x at the sampled sites."""
+    import torch
+    sites, gu = solve_sites
     sol = odwf.Solver(full["lat"], NS, M0, full["w"])
     b = synth.make_source_device(DIMS, NS, 1, 1005)
-    print("full size mixed solve fp32 inner, mq=0.04, tol 1e-10", flush=True)
-    x, st = sol.solve(b, [0.04], [1e-10], inner=odwf.FP32)
+    print(f"full size mixed solve fp32 inner, mq={mq}, tol 1e-10", flush=True)
+    x, st = sol.solve(b, [mq], [1e-10], inner=odwf.FP32)
     sol.close()
     del sol
     torch.cuda.empty_cache()
@@ -126,7 +135,7 @@ def test_fullsize_mixed_solve_sampled_residual(full, src):
     assert st["status"] == odwf.OK and st["true_rel_resid"] <= 1e-10
     bnorm = torch.linalg.vector_norm(b).item()
     gp = sampled.torch_getters(x[0], None)[0]
-    Dx = sampled.oracle_at_sites(oracle.OP_D, sites, DIMS, -1, gp, gu, NS, M0, full["w"], 0.04 / (2 * M0))
+    Dx = sampled.oracle_at_sites(oracle.OP_D, sites, DIMS, -1, gp, gu, NS, M0, full["w"], mq / (2 * M0))
     bS = sampled.at_sites(b[0], sites)
     rS = np.linalg.norm(bS - Dx)
     print(f"  sampled |b - D x| / |b_S| = {rS / np.linalg.norm(bS):.3e}, "
@@ -134,3 +143,5 @@ def test_fullsize_mixed_solve_sampled_residual(full, src):
     assert st["full_rel_resid"] <= 2e-8
     assert rS <= 1.05 * st["full_rel_resid"] * bnorm
     assert rS / np.linalg.norm(bS) <= 1e-6
+    del x, b
+    torch.cuda.empty_cache()

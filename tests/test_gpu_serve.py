@@ -78,3 +78,37 @@ def test_memory_budget_defers_a_request_until_an_engine_is_evicted():
     sol.close()
     lat.close()
     srv.close()
+
+
+def test_serving_configuration_lattices_oracle_spot_check():
+    """The serving configuration's resident lattices, 8^4, 16^4 and 24^4 x 16
+    (eps 0.5, one gauge field each), 12-slot engines, FP32 inner: a short
+    Poisson stream with the configuration's draws (masses from {0.005, 0.04,
+    0.5}, 1-12 right-hand sides, tolerance 1e-8 or 1e-10); one finished
+    request per lattice is checked against the FP64 oracle over the whole
+    lattice (D x = b with the request's mass)."""
+    lattices = {f"{L}^4": {"dims": (L, L, L, L), "Ns": 16, "eps": 0.5, "seed": 0} for L in (8, 16, 24)}
+    srv = Server(lattices, max_slots=12, inner="fp32")
+    reqs = poisson_stream(8, 4.0, list(lattices), seed=40)
+    done = srv.run(reqs, time_limit=200, keep_solutions=True)
+    assert len(done) == 8
+    s = summarize(done, max(r.finished for r in done), srv.admission)
+    print(f"serving 8^4/16^4/24^4 x 16: {s}")
+    assert s["all_converged"]
+    checked = set()
+    for r in done:
+        if r.lattice in checked:
+            continue
+        checked.add(r.lattice)
+        spec = lattices[r.lattice]
+        U = synth.make_gauge_device(spec["dims"], spec["eps"], spec["seed"]).cpu().numpy()
+        b = synth.make_source_device(spec["dims"], spec["Ns"], r.nrhs, r.seed).cpu().numpy()
+        x = r.x.cpu().numpy()
+        w = srv.engines[r.lattice]["sol"].omega
+        i = r.nrhs - 1
+        Dx = oracle.apply(oracle.OP_D, U, x[i], 1.3, w, r.mq / 2.6)
+        fr = np.linalg.norm(b[i] - Dx) / np.linalg.norm(b[i])
+        print(f"  {r.lattice} m_q={r.mq} tol={r.tol:g} nrhs={r.nrhs}: oracle |b - D x|/|b| = {fr:.3e}, "
+              f"latency {r.latency:.3f} s")
+        assert fr < 1e3 * r.tol
+    srv.close()
