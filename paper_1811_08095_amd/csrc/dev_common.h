@@ -469,23 +469,30 @@ struct LanePass {
   static constexpr bool on = ODWF_LANE_PASS && sizeof(R) == 4 && NS == 16;
 };
 
-// DPP16 row controls: lane i reads lane i - n (SHR), i + n (SHL) or (i - n) mod 16 (ROR)
+// DPP16 row controls: lane i reads lane i - n (SHR), i + n (SHL), (i - n) mod 16
+// (ROR) or lane n of its row (NEWBCAST, gfx90a and later)
 constexpr int DPP_SHL(int n) { return 0x100 + n; }
 constexpr int DPP_SHR(int n) { return 0x110 + n; }
 constexpr int DPP_ROR(int n) { return 0x120 + n; }
+constexpr int DPP_NEWBCAST(int n) { return 0x150 + n; }
 
-// value of v in the lane given by CTRL; lanes whose source lies outside the row get `old`
+// value of v in the lane given by CTRL; lanes whose source lies outside the
+// row read 0 (bound_ctrl), so no register has to be preset with an old value
+template <int CTRL>
+__device__ __forceinline__ float row_move0(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+// the same with a chosen value `old` for lanes whose source lies outside the row
 template <int CTRL>
 __device__ __forceinline__ float row_move(float old, float v) {
   return __int_as_float(
       __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-// value of v in lane 15 (LAST) or lane 0 of the lane's row
+// value of v in lane 15 (LAST) or lane 0 of the lane's row: a DPP row
+// broadcast, no trip through the LDS crossbar
 template <bool LAST>
 __device__ __forceinline__ float row_bcast(float v) {
-  // ds_swizzle bit-mask mode on groups of 32: lane' = (lane & 0x10) | (LAST ? 0xF : 0)
-  constexpr int pat = 0x10 | ((LAST ? 0x0F : 0x00) << 5);
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pat));
+  return row_move0<DPP_NEWBCAST(LAST ? 15 : 0)>(v);
 }
 
 // y[c0 .. c0+5] = d y + e y_nb, with y_nb the value of the neighbouring slice
@@ -493,7 +500,7 @@ template <int CTRL>
 __device__ __forceinline__ void lane_mul(cpx<float> (&y)[12], int c0, float d, float e) {
 #pragma unroll
   for (int c = c0; c < c0 + 6; c++) {
-    const float nr = row_move<CTRL>(0.f, y[c].re), ni = row_move<CTRL>(0.f, y[c].im);
+    const float nr = row_move0<CTRL>(y[c].re), ni = row_move0<CTRL>(y[c].im);
     y[c] = {d * y[c].re + e * nr, d * y[c].im + e * ni};
   }
 }
@@ -509,18 +516,19 @@ __device__ __forceinline__ void lane_solve(cpx<float> (&y)[12], int c0, float a)
 #pragma unroll
     for (int c = c0; c < c0 + 6; c++) {
       float pr, pi;
+      // lanes before the start of the scan read 0: their term vanishes
       if (k == 1) {
-        pr = DOWN ? row_move<DPP_SHR(1)>(0.f, y[c].re) : row_move<DPP_SHL(1)>(0.f, y[c].re);
-        pi = DOWN ? row_move<DPP_SHR(1)>(0.f, y[c].im) : row_move<DPP_SHL(1)>(0.f, y[c].im);
+        pr = DOWN ? row_move0<DPP_SHR(1)>(y[c].re) : row_move0<DPP_SHL(1)>(y[c].re);
+        pi = DOWN ? row_move0<DPP_SHR(1)>(y[c].im) : row_move0<DPP_SHL(1)>(y[c].im);
       } else if (k == 2) {
-        pr = DOWN ? row_move<DPP_SHR(2)>(0.f, y[c].re) : row_move<DPP_SHL(2)>(0.f, y[c].re);
-        pi = DOWN ? row_move<DPP_SHR(2)>(0.f, y[c].im) : row_move<DPP_SHL(2)>(0.f, y[c].im);
+        pr = DOWN ? row_move0<DPP_SHR(2)>(y[c].re) : row_move0<DPP_SHL(2)>(y[c].re);
+        pi = DOWN ? row_move0<DPP_SHR(2)>(y[c].im) : row_move0<DPP_SHL(2)>(y[c].im);
       } else if (k == 4) {
-        pr = DOWN ? row_move<DPP_SHR(4)>(0.f, y[c].re) : row_move<DPP_SHL(4)>(0.f, y[c].re);
-        pi = DOWN ? row_move<DPP_SHR(4)>(0.f, y[c].im) : row_move<DPP_SHL(4)>(0.f, y[c].im);
+        pr = DOWN ? row_move0<DPP_SHR(4)>(y[c].re) : row_move0<DPP_SHL(4)>(y[c].re);
+        pi = DOWN ? row_move0<DPP_SHR(4)>(y[c].im) : row_move0<DPP_SHL(4)>(y[c].im);
       } else {
-        pr = DOWN ? row_move<DPP_SHR(8)>(0.f, y[c].re) : row_move<DPP_SHL(8)>(0.f, y[c].re);
-        pi = DOWN ? row_move<DPP_SHR(8)>(0.f, y[c].im) : row_move<DPP_SHL(8)>(0.f, y[c].im);
+        pr = DOWN ? row_move0<DPP_SHR(8)>(y[c].re) : row_move0<DPP_SHL(8)>(y[c].re);
+        pi = DOWN ? row_move0<DPP_SHR(8)>(y[c].im) : row_move0<DPP_SHL(8)>(y[c].im);
       }
       y[c] = {y[c].re + a * pr, y[c].im + a * pi};
     }

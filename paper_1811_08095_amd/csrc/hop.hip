@@ -246,7 +246,7 @@ __device__ __forceinline__ long block_first_site(const HopArgs& a) {
 }
 
 #ifndef ODWF_HOP_GROUP64
-#define ODWF_HOP_GROUP64 1
+#define ODWF_HOP_GROUP64 2
 #endif
 #ifndef ODWF_HOP_GROUP32
 #define ODWF_HOP_GROUP32 2
