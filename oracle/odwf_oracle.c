@@ -37,7 +37,7 @@
  *   - §2 (conjugate gradient): the solve is textbook Hestenes-Stiefel CG on
  *     the Hermitian positive-definite normal operator S_e^dag S_e.
  *
- * Mutation testing: building with -DORACLE_PLANT=k (k = 1..12) plants one
+ * Mutation testing: building with -DORACLE_PLANT=k (k = 1..14) plants one
  * deliberate, plausible mistake (see PLANT below) so that the tests can show
  * that their pins reject it; the normal build never defines it.
  *
@@ -584,6 +584,72 @@ int oracle_dw(const int dims[4], int bc_t, const cplx* U, double m0, int dag, co
 /* (s, spin) matrices, n = 4 Ns, row major: see m5_matrix */
 int oracle_m5_matrix(int Ns, double m0, const double* omega, double mu, int which, cplx* out) {
   return m5_matrix(Ns, m0, omega, mu, which, out);
+}
+
+/* Fermion force of the bilinear S = Re <chi, W psi> (W the hopping term of
+ * D_w, applied slice by slice and summed over s): for every link U_mu(x),
+ *   M = -1/2 b sum_s ( A + B^dag ),
+ *   A[b][a] = sum_spin [(1 - gamma_mu) psi(x + mu, s)]_{spin, b} conj(chi(x, s)_{spin, a}),
+ *   B[b][a] = sum_spin [(1 + gamma_mu) psi(x, s)]_{spin, b} conj(chi(x + mu, s)_{spin, a}),
+ * with b the boundary factor of the link (bc_t when x + mu wraps in t), so
+ * that S contains Re tr(U_mu(x) M) and nothing else depends on U_mu(x); then
+ *   F_mu(x) = TA(U_mu(x) M),   TA(X) = (X - X^dag)/2 - tr(X - X^dag)/6,
+ * which satisfies dS/d eps = i tr(T F_mu(x)) for U_mu(x) -> exp(i eps T) U_mu(x),
+ * T Hermitian and traceless.  chi, psi: [s][t][z][y][x][4][3]; F: [t][z][y][x][mu][3][3]. */
+int oracle_force(const int dims[4], int bc_t, const cplx* U, int Ns, const cplx* chi, const cplx* psi,
+                 cplx* F) {
+  geom_t g = make_geom(dims, bc_t);
+  init_gamma();
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < g.V; x++) {
+    for (int mu = 0; mu < 4; mu++) {
+      double bs;
+      long y = neighbour(&g, x, mu, +1, &bs);
+      cplx A[3][3], B[3][3];
+      memset(A, 0, sizeof(A));
+      memset(B, 0, sizeof(B));
+      for (int s = 0; s < Ns; s++) {
+        const cplx* py = psi + ((long)s * g.V + y) * 12;
+        const cplx* px = psi + ((long)s * g.V + x) * 12;
+        const cplx* cx = chi + ((long)s * g.V + x) * 12;
+        const cplx* cy = chi + ((long)s * g.V + y) * 12;
+        for (int al = 0; al < 4; al++) {
+          cplx vf[3], vb[3];
+          for (int b = 0; b < 3; b++) {
+            vf[b] = 0;
+            vb[b] = 0;
+            for (int be = 0; be < 4; be++) {
+              cplx id = al == be ? 1.0 : 0.0;
+              cplx gm = PLANT(14) ? -G[mu][al][be] : G[mu][al][be];
+              vf[b] += (id - gm) * py[be * 3 + b];
+              vb[b] += (id + gm) * px[be * 3 + b];
+            }
+          }
+          for (int b = 0; b < 3; b++)
+            for (int a = 0; a < 3; a++) {
+              A[b][a] += vf[b] * conj(cx[al * 3 + a]);
+              B[b][a] += vb[b] * conj(cy[al * 3 + a]);
+            }
+        }
+      }
+      cplx M[3][3];
+      for (int b = 0; b < 3; b++)
+        for (int a = 0; a < 3; a++) M[b][a] = -0.5 * bs * (A[b][a] + (PLANT(13) ? 0.0 : conj(B[a][b])));
+      const cplx* u = U + (x * 4 + mu) * 9;
+      cplx X[3][3];
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+          X[a][b] = 0;
+          for (int c = 0; c < 3; c++) X[a][b] += u[a * 3 + c] * M[c][b];
+        }
+      cplx tr = 0;
+      for (int a = 0; a < 3; a++) tr += X[a][a] - conj(X[a][a]);
+      cplx* f = F + (x * 4 + mu) * 9;
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) f[a * 3 + b] = 0.5 * (X[a][b] - conj(X[b][a])) - (a == b ? tr / 6.0 : 0.0);
+    }
+  }
+  return 0;
 }
 
 /* one right-hand side: out = op(in), full-lattice 5D fields */

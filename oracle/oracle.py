@@ -65,6 +65,7 @@ def _open(path):
                                          ctypes.c_double, _f64p, ctypes.c_double,
                                          _c128p, _c128p]
     L.oracle_normal_residual.restype = ctypes.c_double
+    L.oracle_force.argtypes = [_i32p, ctypes.c_int, _c128p, ctypes.c_int, _c128p, _c128p, _c128p]
     L.oracle_num_threads.restype = ctypes.c_int
     return L
 
@@ -137,6 +138,18 @@ def normal_residual(U, f, y, m0, omega, mu, bc_t=-1):
                                         np.ascontiguousarray(omega, np.float64), float(mu),
                                         np.ascontiguousarray(f, np.complex128),
                                         np.ascontiguousarray(y, np.complex128))
+
+
+def force(U, chi, psi, bc_t=-1):
+    """Fermion force F_mu(x) = TA(U_mu(x) M_mu(x)) of S = Re <chi, W psi> (see
+    oracle_force); chi, psi [s][t][z][y][x][4][3]; returns F [t][z][y][x][4][3][3]."""
+    U = np.ascontiguousarray(U, np.complex128)
+    F = np.zeros(U.shape, np.complex128)
+    rc = lib().oracle_force(_dims(U), int(bc_t), U, chi.shape[0], np.ascontiguousarray(chi, np.complex128),
+                            np.ascontiguousarray(psi, np.complex128), F)
+    if rc:
+        raise RuntimeError("oracle_force failed")
+    return F
 
 
 def parity_mask(dims_tzyx):

@@ -15,6 +15,8 @@ Planted mistakes:
  10 even-odd hop entries with output and input parities exchanged
  11 normal-system residual formed as f + N y
  12 site-local A^{-1} applied transposed
+ 13 fermion force without the backward-hop term
+ 14 fermion force with the projector signs exchanged
 
 Exchanging the chiral projectors of L_+ and L_- is not among them: that gives
 R5 D R5 (R5: s -> Ns + 1 - s), the same operator up to relabelling s when
@@ -23,13 +25,15 @@ fixed by the reading of the operator and the GPU path is held to it by parity.
 """
 import pytest
 
+import test_oracle_force as fpins
 import test_oracle_pins as pins
 from oracle import build, oracle
 
 PLANTS = {1: "projector sign", 2: "missing link adjoint", 3: "boundary factor dropped",
           4: "boundary-term sign", 5: "one shift direction for both chiralities", 6: "Wilson mass 5 - m0",
           7: "Schur sign", 8: "hop normalisation", 9: "z hop reversed", 10: "hop parities swapped",
-          11: "normal residual sign", 12: "A^-1 transposed"}
+          11: "normal residual sign", 12: "A^-1 transposed", 13: "force without backward term",
+          14: "force projector sign"}
 
 # every pin, with the arguments its parametrisation uses
 PIN_CALLS = [
@@ -48,6 +52,8 @@ PIN_CALLS = [
     (pins.test_hop_entries_are_parity_blocks_of_dense_wilson, {"dims": (4, 2, 2, 6), "bc_t": -1}),
     (pins.test_m5inv_entry_is_the_site_local_inverse, {}),
     (pins.test_normal_residual_against_dense_schur_from_pinned_blocks, {"bc_t": -1}),
+    (fpins.test_force_is_the_derivative_of_the_bilinear, {"bc_t": -1}),
+    (fpins.test_force_gauge_covariance, {}),
 ]
 
 
