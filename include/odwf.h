@@ -218,6 +218,25 @@ odwf_status odwf_solve_masses(odwf_solver s, const double* mq, const double* tol
                               odwf_prec inner, int maxiter, const void* b, void* y, int use_y0,
                               int per_launch, odwf_stats* stats, void* stream);
 
+/* Fermion-force primitive (paper §2: the forces of the HMC's fermion actions
+ * differentiate bilinears of the hopping term with the solutions of the
+ * normal equations).  For
+ *     S = Re <chi, W psi> = Re sum_s sum_x chi(x, s)^dag (W psi)(x, s),
+ * W the hopping term of D_w (the header's D_w without its 4 - m0 diagonal,
+ * hops across the t boundary times bc_t), every link U_mu(x) enters S only as
+ *     Re tr(U_mu(x) M_mu(x)),   M = -1/2 b (A + B^dag),
+ *     A = sum_{s,spin} [(1 - gamma_mu) psi(x + mu, s)] (x) chi(x, s)^dag,
+ *     B = sum_{s,spin} [(1 + gamma_mu) psi(x, s)] (x) chi(x + mu, s)^dag,
+ * (b = bc_t if x + mu wraps in t, else 1), and the force is
+ *     F_mu(x) = TA(U_mu(x) M_mu(x)),  TA(X) = (X - X^dag)/2 - tr(X - X^dag)/6,
+ * traceless anti-Hermitian, so that dS/d eps = i tr(T F_mu(x)) for
+ * U_mu(x) -> exp(i eps T) U_mu(x) with T Hermitian and traceless.
+ * chi, psi: device canonical spinor fields of ONE right-hand side (Ns * V * 12
+ * complex128); F: device complex128 [t][z][y][x][mu][3][3], overwritten, or
+ * added to when accumulate != 0 (sums of several bilinears).  FP64. */
+odwf_status odwf_force(odwf_solver s, const void* chi, const void* psi, int accumulate, void* F,
+                       void* stream);
+
 /* Allocate now the workspaces odwf_solve uses on `stream` for nrhs right-hand
  * sides (at most one launch's worth, 256 / Ns, is held) in precision `inner`,
  * so that a later solve does no device allocation of its own.  Workspaces are

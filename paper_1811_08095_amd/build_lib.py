@@ -15,8 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libodwf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hop.hip", "pack.hip", "blas.hip", "m5.hip", "noalloc.hip", "runtime.cpp", "api.cpp",
-           "solver.cpp", "batch.cpp"]
+SOURCES = ["hop.hip", "force.hip", "pack.hip", "blas.hip", "m5.hip", "noalloc.hip", "runtime.cpp",
+           "api.cpp", "solver.cpp", "batch.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

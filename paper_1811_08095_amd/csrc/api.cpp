@@ -480,6 +480,32 @@ extern "C" odwf_status odwf_solve_masses(odwf_solver S, const double* mq, const 
   return worst;
 }
 
+extern "C" odwf_status odwf_force(odwf_solver S, const void* chi, const void* psi, int accumulate,
+                                  void* F, void* stream) {
+  REQUIRE(S && chi && psi && F, "odwf_force: null argument");
+  REQUIRE(F != chi && F != psi, "odwf_force: F must not alias chi or psi");
+  REQUIRE(S->lat->loaded, "odwf_force: gauge field not loaded");
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  Workspace& W = S->workspace(st);
+  const Geom& g = S->lat->g;
+  const int Ns = S->Ns;
+  HV ce = W.half("f.ce", g.h, 1, Ns, PREC64), co = W.half("f.co", g.h, 1, Ns, PREC64);
+  HV pe = W.half("f.pe", g.h, 1, Ns, PREC64), po = W.half("f.po", g.h, 1, Ns, PREC64);
+  if (!ce.d || !co.d || !pe.d || !po.d) {
+    set_error("odwf_force: out of device memory for workspaces");
+    return ODWF_ENOMEM;
+  }
+  HIPCHK(launch_pack_spinor(PREC64, chi, 0, ce.d, nullptr, 0, 1, Ns, g, st));
+  HIPCHK(launch_pack_spinor(PREC64, chi, 0, co.d, nullptr, 1, 1, Ns, g, st));
+  HIPCHK(launch_pack_spinor(PREC64, psi, 0, pe.d, nullptr, 0, 1, Ns, g, st));
+  HIPCHK(launch_pack_spinor(PREC64, psi, 0, po.d, nullptr, 1, 1, Ns, g, st));
+  HIPCHK(launch_force(ce.d, pe.d, co.d, po.d, S->lat->U64[0], F, 0, Ns, S->lat->bc_t, accumulate, g, st));
+  HIPCHK(launch_force(co.d, po.d, ce.d, pe.d, S->lat->U64[1], F, 1, Ns, S->lat->bc_t, accumulate, g, st));
+  return ODWF_OK;
+}
+
 extern "C" odwf_status odwf_solver_reserve(odwf_solver S, int nrhs, odwf_prec inner, void* stream) {
   REQUIRE(S, "odwf_solver_reserve: null solver");
   REQUIRE(nrhs >= 1, "odwf_solver_reserve: nrhs must be >= 1");

@@ -282,6 +282,65 @@ __device__ __forceinline__ void store_site(void* base, float* scale, long j, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// spin projection in the chiral basis (shared by the hopping and force kernels)
+// ---------------------------------------------------------------------------
+
+// multiplication by f in {+1, -1, +i, -i} (codes 0..3)
+template <int CODE, class R>
+__device__ __forceinline__ cpx<R> mulf(cpx<R> z) {
+  if constexpr (CODE == 0) return z;
+  if constexpr (CODE == 1) return {-z.re, -z.im};
+  if constexpr (CODE == 2) return {-z.im, z.re};
+  return {z.im, -z.re};
+}
+template <int CODE>
+struct ConjCode {
+  static constexpr int v = CODE == 2 ? 3 : (CODE == 3 ? 2 : CODE);
+};
+
+// chiral basis: gamma_mu = [[0, B_mu], [B_mu^dag, 0]], row a of B_mu has one
+// entry f_a at column p_a:
+//   mu = x: p = (1, 0), f = (-i, -i);   mu = y: p = (1, 0), f = (-1, +1)
+//   mu = z: p = (0, 1), f = (-i, +i);   mu = t: p = (0, 1), f = (+1, +1)
+template <int MU>
+struct GammaB;
+template <>
+struct GammaB<0> {
+  static constexpr int p0 = 1, p1 = 0, f0 = 3, f1 = 3;
+};
+template <>
+struct GammaB<1> {
+  static constexpr int p0 = 1, p1 = 0, f0 = 1, f1 = 0;
+};
+template <>
+struct GammaB<2> {
+  static constexpr int p0 = 0, p1 = 1, f0 = 3, f1 = 2;
+};
+template <>
+struct GammaB<3> {
+  static constexpr int p0 = 0, p1 = 1, f0 = 0, f1 = 0;
+};
+
+// (1 - SIG gamma_mu) psi = [h; -SIG B^dag h], h = psi_up - SIG B psi_dn.
+// Computes the half spinor h (2 spins x 3 colours).
+template <int MU, int SIG, class R>
+__device__ __forceinline__ void project(const cpx<R> (&psi)[12], cpx<R> (&h)[6]) {
+  using B = GammaB<MU>;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    cpx<R> t0 = mulf<B::f0>(psi[(2 + B::p0) * 3 + c]);
+    cpx<R> t1 = mulf<B::f1>(psi[(2 + B::p1) * 3 + c]);
+    if constexpr (SIG > 0) {
+      h[c] = csub(psi[c], t0);
+      h[3 + c] = csub(psi[3 + c], t1);
+    } else {
+      h[c] = cadd(psi[c], t0);
+      h[3 + c] = cadd(psi[3 + c], t1);
+    }
+  }
+}
+
 // is right-hand side r selected by the gate?
 __device__ __forceinline__ bool gate_on(const CGScal* g, int mode, int r) {
   if (!g || mode == GATE_NONE) return true;

@@ -59,6 +59,13 @@ hipError_t launch_vec_norm2(int prec, const void* v, const float* sc, double* pa
                             int nrhs, int Ns, int* nblocks_out, hipStream_t st);
 int vec_nblocks(long h, int nrhs, int Ns);
 
+// fermion force of Re <chi, W psi> on the links of the sites of parity `par`
+// (force.hip): own / nb are FP64 one-right-hand-side halves of chi and psi on
+// parity par and on the other parity; F canonical [t][z][y][x][mu][3][3]
+hipError_t launch_force(const void* chi_own, const void* psi_own, const void* chi_nb, const void* psi_nb,
+                        const void* links, void* F, int par, int Ns, int bc_t, int accumulate, const Geom& g,
+                        hipStream_t st);
+
 // scalar finalisation (blas.hip), one block
 enum FinKind { FIN_SUM = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_INIT = 3, FIN_F2 = 4, FIN_TRUE = 5 };
 // bytes a partial-sum buffer for nblocks blocks needs (includes the second

@@ -61,6 +61,7 @@ SYMBOLS = {
     "odwf_apply_noalloc": ([_vp, _i, _dp, _i, _i, _vp, _vp, _vp], _i),
     "odwf_solve": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_solver_reserve": ([_vp, _i, _i, _vp], _i),
+    "odwf_force": ([_vp, _vp, _vp, _i, _vp, _vp], _i),
     "odwf_solve_masses": ([_vp, _dp, _dp, _i, _i, _i, _vp, _vp, _i, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
     "odwf_zolotarev_omega": ([_i, _d, _d, _dp], _i),
@@ -311,6 +312,20 @@ class Solver:
                                      _stream(stream))
         _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
         return y, [s.as_dict() for s in stats]
+
+    def force(self, chi, psi, F=None, accumulate=False, stream=None):
+        """odwf_force: F_mu(x) = TA(U_mu(x) M_mu(x)) of Re <chi, W psi>; chi, psi
+        [Ns][t][z][y][x][4][3] (or [1][...]) device fields; returns F
+        [t][z][y][x][4][3][3] complex128 (added to F when accumulate)."""
+        import torch
+        for v, nm in ((chi, "chi"), (psi, "psi")):
+            if tuple(v.shape[-7:]) != self.spinor_shape(1)[1:] or v.numel() != int(np.prod(self.spinor_shape(1))):
+                raise ValueError(f"{nm} has the wrong shape")
+        if F is None:
+            F = torch.zeros(self.lattice.shape_tzyx + (4, 3, 3), dtype=torch.complex128, device=chi.device)
+        _check(lib().odwf_force(self._h, _dev_ptr(chi, "chi"), _dev_ptr(psi, "psi"), 1 if accumulate else 0,
+                                _dev_ptr(F, "F"), _stream(stream)))
+        return F
 
     def reserve(self, nrhs, inner, stream=None):
         """Allocate the workspaces of a solve of nrhs right-hand sides now."""
