@@ -218,6 +218,28 @@ odwf_status odwf_solve_masses(odwf_solver s, const double* mq, const double* tol
                               odwf_prec inner, int maxiter, const void* b, void* y, int use_y0,
                               int per_launch, odwf_stats* stats, void* stream);
 
+/* Effective 4D operator (paper §2: the effective 4D operator of the optimal
+ * domain-wall fermion is exactly the shifted Zolotarev optimal rational
+ * approximation of the overlap operator; with the Pauli-Villars normalisation
+ * of Eq. (1)-(2)):
+ *     D_eff(m_q) = (1 + mu)/2 + (1 - mu)/2 gamma5 S(H_w),   mu = m_q / (2 m0),
+ *     S(H) = (1 - prod_s T_s)(1 + prod_s T_s)^{-1},  T_s = (1 - w_s H)(1 + w_s H)^{-1},
+ * computed through the 5D operator with R taking the chirality-plus spins of
+ * slice Ns and the chirality-minus spins of slice 1 (the slices the m_q
+ * boundary term couples), R^T its embedding:
+ *     inverse == 0:  out = D_eff(m_q) q      = R D(m_PV)^{-1} D(m_q) R^T q,
+ *     inverse != 0:  out = D_eff(m_q)^{-1} q = R D(m_q)^{-1} D(m_PV) R^T q
+ *                    (the 4D quark propagator),  m_PV = 2 m0;
+ * one FULL odwf_solve per right-hand side (tolerance tol[r], inner precision,
+ * maxiter, stats as there; apply: the solve is at m_PV, propagator: at
+ * m_q[r]).  q, out: device canonical 4D spinor fields complex128
+ * [rhs][t][z][y][x][spin 4][color 3], distinct.  Workspaces: two canonical 5D
+ * fields of one launch's right-hand sides plus those of the solve.  Returns as
+ * odwf_solve; synchronises with `stream`. */
+odwf_status odwf_deff(odwf_solver s, int inverse, const double* mq, const double* tol, int nrhs,
+                      odwf_prec inner, int maxiter, const void* q, void* out, odwf_stats* stats,
+                      void* stream);
+
 /* Fermion-force primitive (paper §2: the forces of the HMC's fermion actions
  * differentiate bilinears of the hopping term with the solutions of the
  * normal equations).  For

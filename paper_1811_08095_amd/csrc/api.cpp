@@ -480,6 +480,58 @@ extern "C" odwf_status odwf_solve_masses(odwf_solver S, const double* mq, const 
   return worst;
 }
 
+extern "C" odwf_status odwf_deff(odwf_solver S, int inverse, const double* mq, const double* tol, int nrhs,
+                                 odwf_prec inner, int maxiter, const void* q, void* out,
+                                 odwf_stats* stats, void* stream) {
+  REQUIRE(S && mq && tol && q && out, "odwf_deff: null argument");
+  REQUIRE(q != out, "odwf_deff: q and out must be distinct buffers");
+  REQUIRE(nrhs >= 1, "odwf_deff: nrhs must be >= 1");
+  REQUIRE(inner >= ODWF_FP64 && inner <= ODWF_BF16S, "odwf_deff: bad inner precision");
+  REQUIRE(maxiter >= 1, "odwf_deff: maxiter must be >= 1");
+  REQUIRE(S->lat->loaded, "odwf_deff: gauge field not loaded");
+  for (int r = 0; r < nrhs; r++) {
+    REQUIRE(std::isfinite(mq[r]), "odwf_deff: mq must be finite");
+    REQUIRE(tol[r] > 0 && tol[r] < 1, "odwf_deff: tol must be in (0, 1)");
+  }
+  HIPCHK(hipSetDevice(S->lat->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(S->mtx);
+  Workspace& W = S->workspace(st);
+  const Geom& g = S->lat->g;
+  const int Ns = S->Ns;
+  const HalfFn get = [&](const char* name, int n, int p) { return W.half(name, g.h, n, Ns, p); };
+  const int chunk = max_rhs_per_launch(Ns);
+  const double mpv = 2.0 * S->m0;
+  odwf_status worst = ODWF_OK;
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int n = std::min(chunk, nrhs - r0);
+    const size_t bytes5 = (size_t)n * Ns * g.V * 12 * 16;
+    void* phi = W.get("d.phi", bytes5);
+    void* psi = W.get("d.psi", bytes5);
+    if (!phi || !psi) {
+      set_error("odwf_deff: out of device memory for workspaces");
+      return ODWF_ENOMEM;
+    }
+    // D_eff q = R D(m_PV)^{-1} D(m_q) R^T q;  D_eff^{-1} q = R D(m_q)^{-1} D(m_PV) R^T q
+    double ma[MAXRHS], mb[MAXRHS];
+    for (int k = 0; k < n; k++) {
+      ma[k] = inverse ? mpv : mq[r0 + k];
+      mb[k] = inverse ? mq[r0 + k] : mpv;
+    }
+    const size_t off4 = (size_t)r0 * g.V * 12 * 16;
+    HIPCHK(launch_boundary_embed(static_cast<const char*>(q) + off4, phi, n, Ns, g, st));
+    odwf_status sa = apply_chunk(S, ODWF_OP_D, ma, PREC64, 0, n, phi, psi, st, get, false);
+    if (sa != ODWF_OK) return sa;
+    odwf_status ss = solve_chunk(S, ODWF_SOLVE_FULL, mb, tol + r0, 0, n, (int)inner, maxiter, psi, phi, 0,
+                                 stats ? stats + r0 : nullptr, st);
+    if (ss == ODWF_EHIP || ss == ODWF_ENOMEM || ss == ODWF_EINVAL) return ss;
+    if (ss != ODWF_OK && worst == ODWF_OK) worst = ss;
+    HIPCHK(launch_boundary_project(phi, static_cast<char*>(out) + off4, n, Ns, g, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return worst;
+}
+
 extern "C" odwf_status odwf_force(odwf_solver S, const void* chi, const void* psi, int accumulate,
                                   void* F, void* stream) {
   REQUIRE(S && chi && psi && F, "odwf_force: null argument");

@@ -26,6 +26,11 @@ hipError_t launch_unpack_spinor(int prec, const void* in, const float* in_sc, vo
 // zero the sites of parity par of a canonical field (rhs r0 .. r0+nrhs-1)
 hipError_t launch_zero_canon_parity(void* canon, int r0, int par, int nrhs, int Ns, const Geom& g,
                                     hipStream_t st);
+// boundary maps of the effective 4D operator on canonical complex128 fields:
+// embed 4D q [r][site][12] into 5D f [r][s][site][12] (chirality minus into
+// slice 0, plus into slice Ns - 1, zeros elsewhere); project back
+hipError_t launch_boundary_embed(const void* q, void* f, int nrhs, int Ns, const Geom& g, hipStream_t st);
+hipError_t launch_boundary_project(const void* f, void* q, int nrhs, int Ns, const Geom& g, hipStream_t st);
 // gauge: canonical complex128 [t][z][y][x][mu][3][3] -> per-parity link
 // arrays [h][8][18 doubles] (prec64) or [h][8][12 floats] (reduced)
 hipError_t launch_pack_gauge(const void* canon, void* out, int par, int prec, const Geom& g,

@@ -131,6 +131,38 @@ __global__ void pack_gauge_kernel(const double2* __restrict__ canon, void* out, 
   }
 }
 
+// boundary maps of the effective 4D operator, on canonical fields:
+// embed: 5D [r][s][site][spin][colour] from 4D [r][site][spin][colour], the
+//   chirality-minus spins (2, 3) into slice 0, the chirality-plus spins (0, 1)
+//   into slice Ns - 1, zeros elsewhere;
+// project: 4D from 5D, chirality-plus spins of slice Ns - 1 and chirality-minus
+//   spins of slice 0 (the pair of slices the m_q boundary term couples)
+__global__ void boundary_embed_kernel(const double2* __restrict__ q, double2* __restrict__ f, int nrhs,
+                                      int Ns, long V) {
+  const long n = (long)nrhs * Ns * V * 12;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(k % 12);
+    const long site = (k / 12) % V;
+    const int s = (int)((k / (12 * V)) % Ns);
+    const long r = k / (12 * V * Ns);
+    const bool plus = c < 6;
+    const bool take = (s == 0 && !plus) || (s == Ns - 1 && plus);
+    f[k] = take ? q[(r * V + site) * 12 + c] : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void boundary_project_kernel(const double2* __restrict__ f, double2* __restrict__ q, int nrhs,
+                                        int Ns, long V) {
+  const long n = (long)nrhs * V * 12;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(k % 12);
+    const long site = (k / 12) % V;
+    const long r = k / (12 * V);
+    const int s = c < 6 ? Ns - 1 : 0;
+    q[k] = f[((r * Ns + s) * V + site) * 12 + c];
+  }
+}
+
 static GeomK gk(const Geom& g) {
   GeomK k;
   for (int d = 0; d < 4; d++) k.L[d] = g.L[d];
@@ -181,6 +213,20 @@ hipError_t launch_zero_canon_parity(void* canon, int r0, int par, int nrhs, int 
   const long n = g.h * nrhs * Ns;
   hipLaunchKernelGGL(zero_canon_parity_kernel, grid_for(n, 256), dim3(256), 0, st,
                      reinterpret_cast<double2*>(canon), r0, par, nrhs, Ns, gk(g));
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary_embed(const void* q, void* f, int nrhs, int Ns, const Geom& g, hipStream_t st) {
+  const long n = (long)nrhs * Ns * g.V * 12;
+  hipLaunchKernelGGL(boundary_embed_kernel, grid_for(n, 256), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(q), reinterpret_cast<double2*>(f), nrhs, Ns, g.V);
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary_project(const void* f, void* q, int nrhs, int Ns, const Geom& g, hipStream_t st) {
+  const long n = (long)nrhs * g.V * 12;
+  hipLaunchKernelGGL(boundary_project_kernel, grid_for(n, 256), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(q), nrhs, Ns, g.V);
   return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ SYMBOLS = {
     "odwf_solve": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_solver_reserve": ([_vp, _i, _i, _vp], _i),
     "odwf_force": ([_vp, _vp, _vp, _i, _vp, _vp], _i),
+    "odwf_deff": ([_vp, _i, _dp, _dp, _i, _i, _i, _vp, _vp, ctypes.POINTER(Stats), _vp], _i),
     "odwf_solve_masses": ([_vp, _dp, _dp, _i, _i, _i, _vp, _vp, _i, _i, ctypes.POINTER(Stats), _vp], _i),
     "odwf_footprint": ([ctypes.POINTER(ctypes.c_int), _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
     "odwf_zolotarev_omega": ([_i, _d, _d, _dp], _i),
@@ -312,6 +313,24 @@ class Solver:
                                      _stream(stream))
         _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
         return y, [s.as_dict() for s in stats]
+
+    def deff(self, q, mq, tol=1e-12, inverse=False, inner=FP64, maxiter=100000, out=None, stream=None,
+             raise_on_noconv=True):
+        """odwf_deff: D_eff(m_q) q, or D_eff(m_q)^{-1} q with inverse=True, for 4D
+        fields q [rhs][t][z][y][x][4][3]; returns (out, stats of the 5D solves)."""
+        import torch
+        nrhs = q.shape[0]
+        if tuple(q.shape) != (nrhs,) + self.lattice.shape_tzyx + (4, 3):
+            raise ValueError("q has the wrong shape")
+        if out is None:
+            out = torch.empty_like(q)
+        mqa, mqp = _f64arr(np.broadcast_to(np.asarray(mq, np.float64), (nrhs,)))
+        tla, tlp = _f64arr(np.broadcast_to(np.asarray(tol, np.float64), (nrhs,)))
+        stats = (Stats * nrhs)()
+        st = lib().odwf_deff(self._h, 1 if inverse else 0, mqp, tlp, nrhs, int(inner), int(maxiter),
+                             _dev_ptr(q, "q"), _dev_ptr(out, "out"), stats, _stream(stream))
+        _check(st, allow=() if raise_on_noconv else (ENOCONV, ENAN))
+        return out, [s.as_dict() for s in stats]
 
     def force(self, chi, psi, F=None, accumulate=False, stream=None):
         """odwf_force: F_mu(x) = TA(U_mu(x) M_mu(x)) of Re <chi, W psi>; chi, psi
