@@ -157,35 +157,80 @@ __device__ __forceinline__ void hop_one_scaled(const cpx<R> (&psi)[12], R sc, co
 }
 
 // first site of this block under the configured traversal
+//
+// Tiled walk (tile_y, tile_z > 0): a tile is tile_x x-row segments (of spb
+// half-row sites) by tile_y by tile_z rows, walked segment-fastest, then y, z,
+// with t innermost over tile_t slices (all of t when 0), so that the t
+// neighbours a slice reads were fetched by the slices just before it.
+// xcd = 1: hardware dispatches block b to XCD b % 8; XCD x is given the
+// contiguous logical range [start(x), start(x) + count(x)), one run of tiles
+// per XCD.  xcd = 2 (lockstep): the eight XCDs walk the eight tiles of a
+// group of xgy (y) x 8 / xgy (z) adjacent tiles at the same time, block for
+// block, so the halo rows two XCDs share are fetched by both at about the same
+// time and the second read is served by the memory-side cache.
 __device__ __forceinline__ long block_first_site(const HopArgs& a) {
   int lb = blockIdx.x;
-  if (a.xcd) {
-    // hardware dispatches block b to XCD b % 8; give XCD x the contiguous
-    // logical range [start(x), start(x) + count(x))
-    const int q = a.nblocks >> 3, rem = a.nblocks & 7;
-    const int x = lb & 7, k = lb >> 3;
-    lb = x * q + min(x, rem) + k;
-  }
+  const int hx = a.L[0] >> 1;
   if (a.tile_y > 0) {
-    const int hx = a.L[0] >> 1;
     const int nseg = hx / a.spb;
-    int rest = lb;
-    const int seg = rest % nseg;
-    rest /= nseg;
+    const int tx = a.tile_x > 0 ? a.tile_x : nseg;
+    const int tlen = a.tile_t > 0 ? a.tile_t : a.L[3];
+    const int nty = a.L[1] / a.tile_y, ntz = a.L[2] / a.tile_z, ntx = nseg / tx;
+    int rest, tyi, tzi;
+    if (a.xcd == 2) {
+      const int per = tx * a.tile_y * a.tile_z * tlen;  // blocks of one tile
+      const int x = lb & 7, k = lb >> 3;
+      const int xgy = a.xcd_gy, xgz = 8 / a.xcd_gy;
+      const int gy = x % xgy, gz = x / xgy;  // this XCD's tile in the group
+      int r2 = k % per;
+      int grp = k / per;
+      const int seg_i = r2 % tx;
+      r2 /= tx;
+      const int yi = r2 % a.tile_y;
+      r2 /= a.tile_y;
+      const int zi = r2 % a.tile_z;
+      const int tl = r2 / a.tile_z;
+      // groups: xgy x xgz tiles in (y, z), then x tiles, then t chunks
+      const int ngy = nty / xgy, ngz = ntz / xgz;
+      tyi = (grp % ngy) * xgy + gy;
+      grp /= ngy;
+      tzi = (grp % ngz) * xgz + gz;
+      grp /= ngz;
+      const int txi = grp % ntx;
+      const int tc = grp / ntx;
+      const int y = tyi * a.tile_y + yi, z = tzi * a.tile_z + zi, t = tc * tlen + tl;
+      const int seg = txi * tx + seg_i;
+      return (((long)t * a.L[2] + z) * a.L[1] + y) * hx + (long)seg * a.spb;
+    }
+    if (a.xcd) {
+      const int q = a.nblocks >> 3, rem = a.nblocks & 7;
+      const int x = lb & 7, k = lb >> 3;
+      lb = x * q + min(x, rem) + k;
+    }
+    rest = lb;
+    const int seg_i = rest % tx;
+    rest /= tx;
     const int yi = rest % a.tile_y;
     rest /= a.tile_y;
     const int zi = rest % a.tile_z;
     rest /= a.tile_z;
-    const int tlen = a.tile_t > 0 ? a.tile_t : a.L[3];
     const int tl = rest % tlen;
     rest /= tlen;
-    const int nty = a.L[1] / a.tile_y, ntz = a.L[2] / a.tile_z;
-    const int y = (rest % nty) * a.tile_y + yi;
+    tyi = rest % nty;
     rest /= nty;
-    const int z = (rest % ntz) * a.tile_z + zi;
+    tzi = rest % ntz;
     rest /= ntz;
+    const int txi = rest % ntx;
+    rest /= ntx;
+    const int y = tyi * a.tile_y + yi, z = tzi * a.tile_z + zi;
     const int t = rest * tlen + tl;  // rest: index of the t chunk
+    const int seg = txi * tx + seg_i;
     return (((long)t * a.L[2] + z) * a.L[1] + y) * hx + (long)seg * a.spb;
+  }
+  if (a.xcd) {
+    const int q = a.nblocks >> 3, rem = a.nblocks & 7;
+    const int x = lb & 7, k = lb >> 3;
+    lb = x * q + min(x, rem) + k;
   }
   return (long)lb * a.spb;
 }
@@ -315,6 +360,139 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
   return nval;
 }
 
+// The eight hopping terms of output site j, summed into acc (times -1/2).
+// ROW: the block lies inside one x-row (half-row length a multiple of the
+// sites per block), so y, z, t and the parity of the row are block-uniform;
+// every neighbour is then read as a block-uniform row base (64-bit, scalar
+// registers) plus a per-lane 32-bit byte offset, and only three such offsets
+// exist per lane: the own column (y, z, t hops) and the two x neighbours.
+// Otherwise the coordinates and the neighbour index are formed per lane.
+template <class P, int NS, bool DAG, bool ROW>
+__device__ __forceinline__ void hop_sum(const HopArgs& a, long j0, long j, int sl, int r, int s,
+                                        const cpx<typename P::real>* U, cpx<typename P::real> (&acc)[12]) {
+  using R = typename P::real;
+  constexpr int NCG = 12 / P::CPB;
+  const int nrhs = a.nrhs;
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int hx = L0 >> 1;
+  int x, y, z, t;
+  // ROW only: per-lane byte offsets within a row of the chunk and scale arrays
+  unsigned off_own = 0, off_xp = 0, off_xm = 0, soff_own = 0, soff_xp = 0, soff_xm = 0;
+  size_t row_bytes = 0, srow_bytes = 0;
+  if constexpr (ROW) {
+    const int xh0 = (int)j0 % hx;
+    const int row = (int)j0 / hx;
+    y = row % L1;
+    z = (row / L1) % L2;
+    t = row / (L1 * L2);
+    const int p = (y + z + t + a.out_par) & 1;
+    const int xi = xh0 + sl;
+    x = 2 * xi + p;
+    // x + 1 lies in half-row column xi (p = 0) or xi + 1 (p = 1); x - 1 in xi - 1 or xi
+    const int xip = p ? (xi + 1 == hx ? 0 : xi + 1) : xi;
+    const int xim = p ? xi : (xi == 0 ? hx - 1 : xi - 1);
+    auto boff = [&](int q) { return (unsigned)((((q * nrhs + r) * NCG) * NS + s) * 16); };
+    auto soff = [&](int q) { return (unsigned)(((q * nrhs + r) * NS + s) * 4); };
+    off_own = boff(xi);
+    off_xp = boff(xip);
+    off_xm = boff(xim);
+    row_bytes = (size_t)hx * nrhs * NCG * NS * 16;
+    if constexpr (P::SCALED) {
+      soff_own = soff(xi);
+      soff_xp = soff(xip);
+      soff_xm = soff(xim);
+      srow_bytes = (size_t)hx * nrhs * NS * 4;
+    }
+  } else {
+    const int xh = (int)(j % hx);
+    long rest = j / hx;
+    y = (int)(rest % L1);
+    rest /= L1;
+    z = (int)(rest % L2);
+    t = (int)(rest / L2);
+    x = 2 * xh + ((y + z + t + a.out_par) & 1);
+  }
+  const bool flip_f = a.bc_t < 0 && t + 1 == L3;  // forward t hop wraps
+  const bool flip_b = a.bc_t < 0 && t == 0;       // backward t hop wraps
+  constexpr int G = HopGroup<P>::G;
+  // direction order: +x, -x, +y, -y, ... (4-7 are the backward hops)
+#pragma unroll 1
+  for (int g0 = 0; g0 < 8; g0 += G) {
+    cpx<R> psi[G][12];
+    R scl[G];  // per-site scales of the neighbours (scaled formats)
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+      const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);  // 0,4,1,5,2,6,3,7
+      const int mu = dir & 3;
+      const bool fwd = dir < 4;
+      if constexpr (ROW) {
+        int yy = y, zz = z, tt = t;
+        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
+        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
+        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
+        const int nrow = (tt * L2 + zz) * L1 + yy;
+        const unsigned off = mu == 0 ? (fwd ? off_xp : off_xm) : off_own;
+        const unsigned char* base = reinterpret_cast<const unsigned char*>(a.in) + (size_t)nrow * row_bytes;
+        uint4 q[NCG];
+#pragma unroll
+        for (int cg = 0; cg < NCG; cg++)
+          q[cg] = *reinterpret_cast<const uint4*>(base + off + (size_t)cg * NS * 16);
+#pragma unroll
+        for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &psi[k][cg * P::CPB]);
+        if constexpr (P::SCALED) {
+          const unsigned so = mu == 0 ? (fwd ? soff_xp : soff_xm) : soff_own;
+          scl[k] = *reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(a.in_sc) +
+                                                   (size_t)nrow * srow_bytes + so);
+        } else {
+          scl[k] = R(1);
+        }
+      } else {
+        int xx = x, yy = y, zz = z, tt = t;
+        if (mu == 0) xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1);
+        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
+        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
+        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
+        const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
+        if constexpr (P::SCALED) load_site_cached_raw<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k], scl[k]);
+        else load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+      const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);
+      const bool fwd = dir < 4;
+      if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
+        if constexpr (P::SCALED) {
+          scl[k] = -scl[k];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
+        }
+      }
+      // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
+      const bool minus = fwd != DAG;
+      if constexpr (P::SCALED) {
+        const R sc = scl[k];
+        switch (dir & 3) {
+          case 0: if (minus) hop_one_scaled<0, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<0, -1>(psi[k], sc, U + dir * 9, acc); break;
+          case 1: if (minus) hop_one_scaled<1, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<1, -1>(psi[k], sc, U + dir * 9, acc); break;
+          case 2: if (minus) hop_one_scaled<2, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<2, -1>(psi[k], sc, U + dir * 9, acc); break;
+          default: if (minus) hop_one_scaled<3, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<3, -1>(psi[k], sc, U + dir * 9, acc); break;
+        }
+      } else {
+        switch (dir & 3) {
+          case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
+          case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
+          case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
+          default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
+}
+
 // minimum waves per SIMD the register allocation must allow (the fused FP32
 // kernels fit four when their column programs run across lanes)
 #ifndef ODWF_HOP_WAVES32
@@ -386,85 +564,10 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   for (int c = 0; c < 12; c++) acc[c] = {R(0), R(0)};
 
   if (valid) {
-    const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
-    const int hx = L0 >> 1;
-    // site coordinates: when a block lies inside one x-row (always for the
-    // tiled traversal) y, z, t are block-uniform and only x varies by lane
-    int x, y, z, t;
-    if (hx % a.spb == 0) {
-      const int xh0 = (int)(j0 % hx);
-      long rest = j0 / hx;
-      y = (int)(rest % L1);
-      rest /= L1;
-      z = (int)(rest % L2);
-      t = (int)(rest / L2);
-      x = 2 * (xh0 + sl) + ((y + z + t + a.out_par) & 1);
-    } else {
-      const int xh = (int)(j % hx);
-      long rest = j / hx;
-      y = (int)(rest % L1);
-      rest /= L1;
-      z = (int)(rest % L2);
-      t = (int)(rest / L2);
-      x = 2 * xh + ((y + z + t + a.out_par) & 1);
-    }
     const cpx<R>* U = lnk + (size_t)sl * 8 * 9;
-    const bool flip_f = a.bc_t < 0 && t + 1 == L3;  // forward t hop wraps
-    const bool flip_b = a.bc_t < 0 && t == 0;       // backward t hop wraps
-    constexpr int G = HopGroup<P>::G;
-    // direction order: +x, -x, +y, -y, ... (4-7 are the backward hops)
-#pragma unroll 1
-    for (int g0 = 0; g0 < 8; g0 += G) {
-      cpx<R> psi[G][12];
-      R scl[G];  // per-site scales of the neighbours (scaled formats)
-#pragma unroll
-      for (int k = 0; k < G; k++) {
-        const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);  // 0,4,1,5,2,6,3,7
-        const int mu = dir & 3;
-        const bool fwd = dir < 4;
-        int xx = x, yy = y, zz = z, tt = t;
-        if (mu == 0) xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1);
-        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
-        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
-        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
-        const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
-        if constexpr (P::SCALED) load_site_cached_raw<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k], scl[k]);
-        else load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < G; k++) {
-        const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);
-        const bool fwd = dir < 4;
-        if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
-          if constexpr (P::SCALED) {
-            scl[k] = -scl[k];
-          } else {
-#pragma unroll
-            for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
-          }
-        }
-        // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
-        const bool minus = fwd != DAG;
-        if constexpr (P::SCALED) {
-          const R sc = scl[k];
-          switch (dir & 3) {
-            case 0: if (minus) hop_one_scaled<0, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<0, -1>(psi[k], sc, U + dir * 9, acc); break;
-            case 1: if (minus) hop_one_scaled<1, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<1, -1>(psi[k], sc, U + dir * 9, acc); break;
-            case 2: if (minus) hop_one_scaled<2, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<2, -1>(psi[k], sc, U + dir * 9, acc); break;
-            default: if (minus) hop_one_scaled<3, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<3, -1>(psi[k], sc, U + dir * 9, acc); break;
-          }
-        } else {
-          switch (dir & 3) {
-            case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
-            case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
-            case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
-            default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
+    // (row offsets are 32-bit: a row of a half field is at most 3 MB here)
+    if ((a.L[0] >> 1) % a.spb == 0 && a.L[0] <= 256) hop_sum<P, NS, DAG, true>(a, j0, j, sl, r, s, U, acc);
+    else hop_sum<P, NS, DAG, false>(a, j0, j, sl, r, s, U, acc);
   }
   if constexpr (PLAIN) {
     if (valid) store_site<P, ODWF_NT_STORE>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);

@@ -105,12 +105,14 @@ struct HopArgs {
   int L[4];
   int nblocks;
   // block traversal: xcd != 0 gives each of the 8 XCDs a contiguous range of
-  // logical blocks; tile_y, tile_z > 0 walk (x-row segment, y, z) tiles with t
-  // innermost so that t-neighbours are re-read while still in L2; tile_t > 0
-  // cuts t into chunks of that length, each chunk walking all (y, z) tiles
-  // before the next chunk starts, so that a tile's y/z halo rows are re-read
-  // by the adjacent tile soon after they were fetched
-  int xcd, tile_y, tile_z, tile_t;
+  // logical blocks, xcd = 2 walks groups of 8 adjacent (y, z) tiles with one
+  // tile per XCD in lockstep; tile_y, tile_z > 0 walk (x-row segments,
+  // y, z) tiles with t innermost so that t-neighbours are re-read while still
+  // in L2; tile_x > 0 is the number of x-row segments of a tile (all of the
+  // row when 0); tile_t > 0 cuts t into chunks of that length, each chunk
+  // walking all tiles before the next chunk starts
+  int xcd, tile_y, tile_z, tile_t, tile_x;
+  int xcd_gy;  // xcd = 2: tiles of a lockstep group along y (1, 2, 4 or 8)
   // t-sweep kernel: > 0 is the number of consecutive t each block walks for
   // its (x-row segment, y, z) column; 0 selects the one-t-per-block kernel
   int sweep;

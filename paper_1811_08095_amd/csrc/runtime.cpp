@@ -108,16 +108,23 @@ static size_t site_bytes(int prec) {
 }
 
 // ---- block traversal of the hopping kernel -------------------------------------
-// Defaults: XCD-aware contiguous block ranges, and a t-innermost walk over
-// (y, z) tiles when the x-rows split evenly into blocks.  ODWF_TRAVERSAL
-// ("linear", "xcd", "Ty,Tz" or "Ty,Tz,Tt") overrides for tuning.
+// Default, when the x-rows split evenly into blocks: tiles of one x-row
+// segment by 8 (4 when Ly is not a multiple of 8) by 4 rows in (y, z), t
+// innermost, the eight XCDs walking a group of 4 x 2 adjacent tiles in
+// lockstep (other group shapes, then contiguous XCD ranges, when the tile
+// counts do not divide).  Otherwise XCD-aware contiguous block ranges.
+// ODWF_TRAVERSAL ("linear", "xcd", "Ty,Tz", "Ty,Tz,Tt" or "Ty,Tz,Tt,Tx"; Tx = 0
+// is the whole row) and ODWF_XCD ("contiguous", "lockstep" or "lockstep:Gy",
+// Gy the tiles of a group along y) override for tuning.
 static void traversal(HopArgs& a, int Ns) {
   const int inner = a.nrhs * Ns;
   const int spb = 256 / inner;
   const int hx = a.L[0] / 2;
   a.xcd = 1;
-  a.tile_y = a.tile_z = a.tile_t = 0;
-  int ty = 4, tz = 4, tt = 0;
+  a.tile_y = a.tile_z = a.tile_t = a.tile_x = 0;
+  a.xcd_gy = 4;
+  int ty = a.L[1] % 8 == 0 ? 8 : 4, tz = 4, tt = 0, tx = 1, gy = 4;
+  bool lockstep = true;
   const char* env = getenv("ODWF_TRAVERSAL");
   if (env) {
     if (!strcmp(env, "linear")) {
@@ -125,14 +132,32 @@ static void traversal(HopArgs& a, int Ns) {
       return;
     }
     if (!strcmp(env, "xcd")) return;
-    const int n = sscanf(env, "%d,%d,%d", &ty, &tz, &tt);
+    const int n = sscanf(env, "%d,%d,%d,%d", &ty, &tz, &tt, &tx);
     if (n < 2) return;
     if (n < 3) tt = 0;
+    if (n < 4) tx = 0;
+  }
+  if (const char* xe = getenv("ODWF_XCD")) {
+    lockstep = !strncmp(xe, "lockstep", 8);
+    if (lockstep && xe[8] == ':') gy = atoi(xe + 9);
   }
   if (ty > 0 && tz > 0 && hx % spb == 0 && a.L[1] % ty == 0 && a.L[2] % tz == 0) {
+    const int nseg = hx / spb;
     a.tile_y = ty;
     a.tile_z = tz;
     if (tt > 0 && a.L[3] % tt == 0) a.tile_t = tt;
+    if (tx > 0 && nseg % tx == 0) a.tile_x = tx;
+    if (lockstep) {
+      const int nty = a.L[1] / ty, ntz = a.L[2] / tz;
+      const int pref[5] = {gy, 4, 2, 8, 1};
+      for (int g : pref) {
+        if ((g == 1 || g == 2 || g == 4 || g == 8) && nty % g == 0 && ntz % (8 / g) == 0) {
+          a.xcd = 2;
+          a.xcd_gy = g;
+          break;
+        }
+      }
+    }
   }
   // t-sweep kernel: blocks walk sweep consecutive t of one column
   a.sweep = 0;

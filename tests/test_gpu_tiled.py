@@ -1,8 +1,12 @@
-"""Whole-lattice GPU parity on lattices that take the hopping kernel's default
-traversal: XCD-aware block ranges over (x-row segment, y, z) tiles of 4 x 4
-with t innermost, which the library selects when Lx/2 is a multiple of the
-sites per block (256 / (nrhs Ns)) and Ly, Lz are multiples of 4 -- the
-traversal of the 64^3 x 64 x 16 benchmark lattice.
+"""Whole-lattice GPU parity on lattices that take the hopping kernel's tiled
+traversal: (x-row segment, y, z) tiles with t innermost, which the library
+selects when Lx/2 is a multiple of the sites per block (256 / (nrhs Ns)) and
+Ly, Lz are multiples of the tile sides (8 or 4 by 4 by default) -- the
+traversal of the 64^3 x 64 x 16 benchmark lattice, where the eight XCDs also
+walk groups of adjacent tiles in lockstep.  The other traversals (lockstep
+groups of several shapes, t chunks, whole-row tiles, linear) are forced
+through the library's tuning variables and must give bitwise the same
+operator results: the traversal only changes which block computes a site.
 
 Every operator is compared with the FP64 CPU oracle element by element:
 normwise |out - ref| / |ref| and per site, max over 5D sites of
@@ -33,6 +37,18 @@ _cache = {}
 def takes_tiled_traversal(dims, Ns, nrhs):
     spb = 256 // (nrhs * Ns)
     return (dims[0] // 2) % spb == 0 and dims[1] % 4 == 0 and dims[2] % 4 == 0
+
+
+# (name, ODWF_TRAVERSAL, ODWF_XCD); on DIMS the 2 x 2 tiles give 4 x 4 tiles in
+# (y, z), so lockstep groups of 4 x 2 and 2 x 4 tiles exist
+TRAVERSALS = [
+    ("default", None, None),
+    ("lockstep 4x2 groups of 2x2 one-segment tiles", "2,2,0,1", "lockstep:4"),
+    ("lockstep 2x4 groups, t chunks of 4", "2,2,4,1", "lockstep:2"),
+    ("contiguous XCD ranges, 4x4 whole-row tiles", "4,4,0,0", "contiguous"),
+    ("contiguous XCD ranges, no tiles", "xcd", None),
+    ("linear", "linear", None),
+]
 
 
 def _setup(bc):
@@ -96,3 +112,39 @@ def test_reduced_precision_tiled(opi, nrhs, prec):
         print(f"{odwf.PREC_NAMES[prec]} {OP_NAMES[opi]} nrhs={nrhs} rhs {r}: normwise {en:.3e}, "
               f"per-site max {es:.3e} (vs FP64 oracle)")
         assert 0 < en <= bn and es <= bs, (en, es)
+
+
+@pytest.mark.parametrize("prec", [odwf.FP64, odwf.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("nrhs", [1, 2], ids=["nrhs1", "nrhs2"])
+def test_traversals_bitwise_identical(monkeypatch, nrhs, prec):
+    bc = -1
+    U, w, lat, sol, psi, psid, refs = _setup(bc)
+    first = {}
+    for name, trav, xcd in TRAVERSALS:
+        if trav is None:
+            monkeypatch.delenv("ODWF_TRAVERSAL", raising=False)
+        else:
+            monkeypatch.setenv("ODWF_TRAVERSAL", trav)
+        if xcd is None:
+            monkeypatch.delenv("ODWF_XCD", raising=False)
+        else:
+            monkeypatch.setenv("ODWF_XCD", xcd)
+        print(f"traversal {name}: {DIMS} Ns={NS} nrhs={nrhs} {odwf.PREC_NAMES[prec]}", flush=True)
+        for opi in (0, 1, 8):
+            out = sol.apply(OPS[opi], psid[:nrhs].contiguous(), MASSES[:nrhs], prec=prec)
+            if opi not in first:
+                first[opi] = out
+                bound = 1e-12 if prec == odwf.FP64 else PREC_BOUND[prec][0]
+                o = out.cpu().numpy()
+                for r in range(nrhs):
+                    en, es = errors(o[r], _ref(bc, opi, r))
+                    assert en <= bound and es <= max(bound, PREC_BOUND.get(prec, (0, 1e-12))[1]), (en, es)
+            else:
+                assert torch_equal(out, first[opi]), (name, OP_NAMES[opi])
+    monkeypatch.delenv("ODWF_TRAVERSAL", raising=False)
+    monkeypatch.delenv("ODWF_XCD", raising=False)
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
