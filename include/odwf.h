@@ -43,12 +43,15 @@
  *     share a buffer.  A batch is used from one thread at a time.
  *   - Tuning (environment, read at every hopping-kernel launch; results do not
  *     depend on them beyond rounding order of the partial sums):
- *       ODWF_TRAVERSAL = "linear" | "xcd" | "Ty,Tz" | "Ty,Tz,Tt"  block order of
- *         the hopping kernel (default "4,4": XCD-aware ranges, (y, z) tiles of
- *         4 x 4 walked with t innermost; Tt > 0 cuts t into chunks of Tt);
- *       ODWF_SWEEP = n  blocks walk n consecutive t of one x-row segment and
- *         carry the own column in registers (used when Lx/2 is a multiple of
- *         256 / (nrhs Ns) sites and n divides Lt; default off).
+ *       ODWF_TRAVERSAL = "linear" | "xcd" | "Ty,Tz" | "Ty,Tz,Tt" | "Ty,Tz,Tt,Tx"
+ *         block order of the hopping kernel.  Default, when the x half-rows
+ *         split into whole blocks: tiles of one x-row segment by 8 x 4 (y, z)
+ *         rows (4 x 4 when Ly is not a multiple of 8) walked with t innermost;
+ *         Tt > 0 cuts t into chunks of Tt, Tx is the number of x-row segments
+ *         per tile (0: the whole row).  Otherwise XCD-aware contiguous ranges;
+ *       ODWF_XCD = "contiguous" | "lockstep" | "lockstep:Gy"  how the eight
+ *         XCDs share the tiles: contiguous runs of tiles, or (default) groups
+ *         of Gy x 8/Gy adjacent tiles walked by the eight XCDs in lockstep.
  */
 #ifndef ODWF_H
 #define ODWF_H

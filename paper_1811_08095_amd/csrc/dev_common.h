@@ -204,28 +204,6 @@ __device__ __forceinline__ void load_site_cached(const void* base, const float* 
   }
 }
 
-// load of site (row + xi): the row's first site `row` is the same for the
-// whole block (a uniform 64-bit base), the position xi in the row is per lane
-// (a 32-bit offset), which keeps the address arithmetic out of vector registers
-template <class P>
-__device__ __forceinline__ void load_site_row(const void* base, const float* scale, long row, int xi,
-                                              int r, int s, int nrhs, int Ns,
-                                              cpx<typename P::real> (&v)[12]) {
-  constexpr int NCG = 12 / P::CPB;
-  const uint4* b = reinterpret_cast<const uint4*>(base) + row * (long)(nrhs * NCG * Ns);
-  const int off = ((xi * nrhs + r) * NCG) * Ns + s;
-  uint4 q[NCG];
-#pragma unroll
-  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
-#pragma unroll
-  for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
-  if constexpr (P::SCALED) {
-    const float sc = scale[row * (long)(nrhs * Ns) + (xi * nrhs + r) * Ns + s];
-#pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = cscale(sc, v[c]);
-  }
-}
-
 // cached neighbour read without the per-site scale applied: v holds the
 // stored values, *sc the site's scale (1 for unscaled formats), so that the
 // caller can apply the scale after its linear algebra on fewer numbers

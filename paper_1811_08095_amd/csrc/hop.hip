@@ -20,6 +20,8 @@
 // U_mu(x - mu)^dag).  Fifth-dimension programs run in LDS on columns
 // (site, r, colour-spin component) of Ns values.  No MFMA: the stencil is a
 // string of 3x3 complex mat-vecs and is bound by HBM bandwidth.
+#include <type_traits>
+
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -48,7 +50,9 @@ struct LinkFmt<SP16> : LinkF12 {};
 template <>
 struct LinkFmt<SPB16> : LinkF12 {};
 
-// stage the links of `nsb` sites starting at j0 into LDS as 9 complex per matrix
+// stage the links of `nsb` sites starting at j0 into LDS as 9 complex per
+// matrix, times -1/2 (the factor of the hopping term: a power of two, so the
+// hop sums round exactly as with the factor applied at the end)
 template <class P>
 __device__ __forceinline__ void stage_links(const void* links, long j0, int nsb,
                                             cpx<typename P::real>* lnk) {
@@ -61,7 +65,7 @@ __device__ __forceinline__ void stage_links(const void* links, long j0, int nsb,
       uint4 v = src[q];
       cpx<double> z;
       unpack_chunk<SP64>(v, &z);
-      lnk[q] = z;
+      lnk[q] = cscale(-0.5, z);
     }
   } else {
     const float4* src = reinterpret_cast<const float4*>(links) + j0 * 8 * 3;
@@ -80,13 +84,13 @@ __device__ __forceinline__ void stage_links(const void* links, long j0, int nsb,
       cpx<float> u[6] = {{a.x, a.y}, {a.z, a.w}, {b.x, b.y}, {b.z, b.w}, {c.x, c.y}, {c.z, c.w}};
       cpx<R>* d = lnk + m * 9;
 #pragma unroll
-      for (int k = 0; k < 6; k++) d[k] = u[k];
+      for (int k = 0; k < 6; k++) d[k] = cscale(-0.5f, u[k]);
       // row2[a] = conj(row0[b] row1[c] - row0[c] row1[b]), (a, b, c) cyclic
 #pragma unroll
       for (int a0 = 0; a0 < 3; a0++) {
         const int b0 = (a0 + 1) % 3, c0 = (a0 + 2) % 3;
         cpx<float> t = csub(cmul(u[b0], u[3 + c0]), cmul(u[c0], u[3 + b0]));
-        d[6 + a0] = {t.re, -t.im};
+        d[6 + a0] = {-0.5f * t.re, 0.5f * t.im};
       }
     }
   }
@@ -360,58 +364,207 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
   return nval;
 }
 
-// The eight hopping terms of output site j, summed into acc (times -1/2).
-// ROW: the block lies inside one x-row (half-row length a multiple of the
-// sites per block), so y, z, t and the parity of the row are block-uniform;
-// every neighbour is then read as a block-uniform row base (64-bit, scalar
-// registers) plus a per-lane 32-bit byte offset, and only three such offsets
-// exist per lane: the own column (y, z, t hops) and the two x neighbours.
-// Otherwise the coordinates and the neighbour index are formed per lane.
-template <class P, int NS, bool DAG, bool ROW>
-__device__ __forceinline__ void hop_sum(const HopArgs& a, long j0, long j, int sl, int r, int s,
+// FP16 storage: the spin projection reads the stored halves directly.  Each
+// real of h = psi_up -/+ f psi_dn (f in {+-1, +-i}) is one fma(+-1, dn, up) of
+// the two halves (v_fma_mix_f32 converts and adds in one instruction); it
+// rounds exactly as the sum of the converted values.  `one` is 1.0 held where
+// the compiler cannot fold it (a product by the literal 1.0 would turn back
+// into a conversion and an add).
+template <int CODE, int SIG>
+__device__ __forceinline__ cpx<float> proj_h16(uint32_t up, uint32_t dn, float one) {
+  const __half2 u = *reinterpret_cast<const __half2*>(&up), d = *reinterpret_cast<const __half2*>(&dn);
+  const float ur = __low2float(u), ui = __high2float(u), dr = __low2float(d), di = __high2float(d);
+  const float m = SIG > 0 ? -one : one;  // h = up + m (f dn)
+  if constexpr (CODE == 0) return {fmaf(m, dr, ur), fmaf(m, di, ui)};
+  if constexpr (CODE == 1) return {fmaf(-m, dr, ur), fmaf(-m, di, ui)};
+  if constexpr (CODE == 2) return {fmaf(-m, di, ur), fmaf(m, dr, ui)};
+  return {fmaf(m, di, ur), fmaf(-m, dr, ui)};
+}
+template <int MU, int SIG>
+__device__ __forceinline__ void hop_one_h16(const uint32_t (&w)[12], float sc, float one, const cpx<float>* U,
+                                            cpx<float> (&acc)[12]) {
+  using B = GammaB<MU>;
+  cpx<float> h[6], g[6];
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    h[c] = proj_h16<B::f0, SIG>(w[c], w[(2 + B::p0) * 3 + c], one);
+    h[3 + c] = proj_h16<B::f1, SIG>(w[3 + c], w[(2 + B::p1) * 3 + c], one);
+  }
+  su3_mul(U, h, g);
+#pragma unroll
+  for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
+  reconstruct<MU, SIG>(g, acc);
+}
+template <bool DAG>
+__device__ __forceinline__ void hop_dir_h16(int dir, const uint32_t (&w)[12], float sc, float one,
+                                            const cpx<float>* U, cpx<float> (&acc)[12]) {
+  const bool minus = (dir < 4) != DAG;
+  const cpx<float>* Ud = U + dir * 9;
+  switch (dir & 3) {
+    case 0: if (minus) hop_one_h16<0, +1>(w, sc, one, Ud, acc); else hop_one_h16<0, -1>(w, sc, one, Ud, acc); break;
+    case 1: if (minus) hop_one_h16<1, +1>(w, sc, one, Ud, acc); else hop_one_h16<1, -1>(w, sc, one, Ud, acc); break;
+    case 2: if (minus) hop_one_h16<2, +1>(w, sc, one, Ud, acc); else hop_one_h16<2, -1>(w, sc, one, Ud, acc); break;
+    default: if (minus) hop_one_h16<3, +1>(w, sc, one, Ud, acc); else hop_one_h16<3, -1>(w, sc, one, Ud, acc); break;
+  }
+}
+
+// one neighbour's hopping term: acc += (1 -/+ gamma_mu) U psi for the
+// direction dir (0-3 forward, 4-7 backward); the scaled formats carry the
+// neighbour's per-site scale sc separately
+template <class P, bool DAG>
+__device__ __forceinline__ void hop_dir(int dir, const cpx<typename P::real> (&psi)[12], typename P::real sc,
                                         const cpx<typename P::real>* U, cpx<typename P::real> (&acc)[12]) {
+  // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
+  const bool minus = (dir < 4) != DAG;
+  const cpx<typename P::real>* Ud = U + dir * 9;
+  if constexpr (P::SCALED) {
+    switch (dir & 3) {
+      case 0: if (minus) hop_one_scaled<0, +1>(psi, sc, Ud, acc); else hop_one_scaled<0, -1>(psi, sc, Ud, acc); break;
+      case 1: if (minus) hop_one_scaled<1, +1>(psi, sc, Ud, acc); else hop_one_scaled<1, -1>(psi, sc, Ud, acc); break;
+      case 2: if (minus) hop_one_scaled<2, +1>(psi, sc, Ud, acc); else hop_one_scaled<2, -1>(psi, sc, Ud, acc); break;
+      default: if (minus) hop_one_scaled<3, +1>(psi, sc, Ud, acc); else hop_one_scaled<3, -1>(psi, sc, Ud, acc); break;
+    }
+  } else {
+    switch (dir & 3) {
+      case 0: if (minus) hop_one<0, +1>(psi, Ud, acc); else hop_one<0, -1>(psi, Ud, acc); break;
+      case 1: if (minus) hop_one<1, +1>(psi, Ud, acc); else hop_one<1, -1>(psi, Ud, acc); break;
+      case 2: if (minus) hop_one<2, +1>(psi, Ud, acc); else hop_one<2, -1>(psi, Ud, acc); break;
+      default: if (minus) hop_one<3, +1>(psi, Ud, acc); else hop_one<3, -1>(psi, Ud, acc); break;
+    }
+  }
+}
+
+// a block-uniform integer in a scalar register (the compiler does not always
+// prove uniformity through the traversal arithmetic)
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The eight hopping terms of output site j0 + sl of a block that lies inside
+// one x-row (half-row length a multiple of the sites per block), summed into
+// acc (the factor -1/2 rides on the staged links).  y, z, t and the parity of
+// the row are then block-uniform: the seven neighbour rows (own row for the x
+// hops, y +- 1, z +- 1, t +- 1) are scalar 64-bit bases, and a lane addresses a
+// neighbour as base + one of three 32-bit offsets (own column, x + 1, x - 1)
+// + a constant chunk offset, so the loads need almost no vector address
+// arithmetic.  Terms are summed in the order +x, -x, +y, -y, +z, -z, +t, -t,
+// the neighbours loaded G at a time ahead of their arithmetic.
+template <class P, int NS, bool DAG>
+__device__ __forceinline__ void hop_sum_row(const HopArgs& a, int j0, int sl, int r, int s,
+                                            const cpx<typename P::real>* U, cpx<typename P::real> (&acc)[12]) {
   using R = typename P::real;
   constexpr int NCG = 12 / P::CPB;
   const int nrhs = a.nrhs;
+  const int L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int hx = a.L[0] >> 1;
+  const int jb = uniform_int(j0);
+  const int xh0 = jb % hx;
+  const int row = jb / hx;
+  const int y = row % L1;
+  const int z = (row / L1) % L2;
+  const int t = row / (L1 * L2);
+  const int p = (y + z + t + a.out_par) & 1;
+  const int yp = y + 1 == L1 ? 0 : y + 1, ym = y == 0 ? L1 - 1 : y - 1;
+  const int zp = z + 1 == L2 ? 0 : z + 1, zm = z == 0 ? L2 - 1 : z - 1;
+  const int tp = t + 1 == L3 ? 0 : t + 1, tm = t == 0 ? L3 - 1 : t - 1;
+  // per lane: half-row column of the own site and of its x neighbours
+  // (x + 1 lies in column xi (p = 0) or xi + 1 (p = 1); x - 1 in xi - 1 or xi)
+  const int xi = xh0 + sl;
+  const int xip = p ? (xi + 1 == hx ? 0 : xi + 1) : xi;
+  const int xim = p ? xi : (xi == 0 ? hx - 1 : xi - 1);
+  auto boff = [&](int q) { return (unsigned)((((q * nrhs + r) * NCG) * NS + s) * 16); };
+  const unsigned off_own = boff(xi), off_xp = boff(xip), off_xm = boff(xim);
+  const size_t row_bytes = (size_t)hx * nrhs * NCG * NS * 16;
+  auto soff = [&](int q) { return (unsigned)(((q * nrhs + r) * NS + s) * 4); };
+  const unsigned soff_own = soff(xi), soff_xp = soff(xip), soff_xm = soff(xim);
+  const size_t srow_bytes = (size_t)hx * nrhs * NS * 4;
+  const bool flip_f = a.bc_t < 0 && t + 1 == L3;  // forward t hop wraps
+  const bool flip_b = a.bc_t < 0 && t == 0;       // backward t hop wraps
+  const unsigned char* in = reinterpret_cast<const unsigned char*>(a.in);
+  const unsigned char* in_sc = reinterpret_cast<const unsigned char*>(a.in_sc);
+  // FP16 neighbours stay packed until the projection (see proj_h16)
+  constexpr bool RAW16 = std::is_same<P, SP16>::value;
+  using Nb = typename std::conditional<RAW16, uint32_t[12], cpx<R>[12]>::type;
+  float one = 1.0f;
+  if constexpr (RAW16) asm("s_mov_b32 %0, 1.0" : "=s"(one));
+  // neighbour of direction dir (0-3 forward, 4-7 backward) into v; sc its scale
+  auto load_nb = [&](int dir, Nb& v, R& sc) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    const int yy = mu == 1 ? (fwd ? yp : ym) : y;
+    const int zz = mu == 2 ? (fwd ? zp : zm) : z;
+    const int tt = mu == 3 ? (fwd ? tp : tm) : t;
+    const int nrow = (tt * L2 + zz) * L1 + yy;  // block-uniform
+    const unsigned off = mu == 0 ? (fwd ? off_xp : off_xm) : off_own;
+    const unsigned char* base = in + (size_t)nrow * row_bytes;
+    uint4 q[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; cg++) q[cg] = *reinterpret_cast<const uint4*>(base + off + cg * NS * 16);
+    if constexpr (RAW16) {
+#pragma unroll
+      for (int cg = 0; cg < NCG; cg++) {
+        v[cg * 4 + 0] = q[cg].x;
+        v[cg * 4 + 1] = q[cg].y;
+        v[cg * 4 + 2] = q[cg].z;
+        v[cg * 4 + 3] = q[cg].w;
+      }
+    } else {
+#pragma unroll
+      for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
+    }
+    if constexpr (P::SCALED) {
+      const unsigned so = mu == 0 ? (fwd ? soff_xp : soff_xm) : soff_own;
+      sc = *reinterpret_cast<const float*>(in_sc + (size_t)nrow * srow_bytes + so);
+    } else {
+      sc = R(1);
+    }
+  };
+  // its hopping term, with the boundary sign of a wrapping t hop
+  auto apply_nb = [&](int dir, Nb& v, R sc) {
+    if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
+      if constexpr (P::SCALED) {
+        sc = -sc;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] = {-v[c].re, -v[c].im};
+      }
+    }
+    if constexpr (RAW16) hop_dir_h16<DAG>(dir, v, sc, one, U, acc);
+    else hop_dir<P, DAG>(dir, v, sc, U, acc);
+  };
+  constexpr int G = HopGroup<P>::G;
+  // direction of the k-th term: 0, 4, 1, 5, 2, 6, 3, 7
+  auto dir_of = [](int k) { return (k >> 1) | ((k & 1) << 2); };
+  // (a rolled loop: unrolled, the compiler issues the loads of later groups
+  // early and spills them at the register budget of four waves per SIMD; a
+  // software pipeline over two register buffers fits three waves and was
+  // slower in the fused kernels)
+#pragma unroll 1
+  for (int g0 = 0; g0 < 8; g0 += G) {
+    Nb psi[G];
+    R scl[G];
+#pragma unroll
+    for (int k = 0; k < G; k++) load_nb(dir_of(g0 + k), psi[k], scl[k]);
+#pragma unroll
+    for (int k = 0; k < G; k++) apply_nb(dir_of(g0 + k), psi[k], scl[k]);
+  }
+}
+
+// The eight hopping terms of output site j, summed into acc (the factor -1/2
+// rides on the staged links), for any block shape: the coordinates and the
+// neighbour index are formed per lane.
+template <class P, int NS, bool DAG>
+__device__ __forceinline__ void hop_sum(const HopArgs& a, long j, int r, int s,
+                                        const cpx<typename P::real>* U, cpx<typename P::real> (&acc)[12]) {
+  using R = typename P::real;
+  const int nrhs = a.nrhs;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
   const int hx = L0 >> 1;
-  int x, y, z, t;
-  // ROW only: per-lane byte offsets within a row of the chunk and scale arrays
-  unsigned off_own = 0, off_xp = 0, off_xm = 0, soff_own = 0, soff_xp = 0, soff_xm = 0;
-  size_t row_bytes = 0, srow_bytes = 0;
-  if constexpr (ROW) {
-    const int xh0 = (int)j0 % hx;
-    const int row = (int)j0 / hx;
-    y = row % L1;
-    z = (row / L1) % L2;
-    t = row / (L1 * L2);
-    const int p = (y + z + t + a.out_par) & 1;
-    const int xi = xh0 + sl;
-    x = 2 * xi + p;
-    // x + 1 lies in half-row column xi (p = 0) or xi + 1 (p = 1); x - 1 in xi - 1 or xi
-    const int xip = p ? (xi + 1 == hx ? 0 : xi + 1) : xi;
-    const int xim = p ? xi : (xi == 0 ? hx - 1 : xi - 1);
-    auto boff = [&](int q) { return (unsigned)((((q * nrhs + r) * NCG) * NS + s) * 16); };
-    auto soff = [&](int q) { return (unsigned)(((q * nrhs + r) * NS + s) * 4); };
-    off_own = boff(xi);
-    off_xp = boff(xip);
-    off_xm = boff(xim);
-    row_bytes = (size_t)hx * nrhs * NCG * NS * 16;
-    if constexpr (P::SCALED) {
-      soff_own = soff(xi);
-      soff_xp = soff(xip);
-      soff_xm = soff(xim);
-      srow_bytes = (size_t)hx * nrhs * NS * 4;
-    }
-  } else {
-    const int xh = (int)(j % hx);
-    long rest = j / hx;
-    y = (int)(rest % L1);
-    rest /= L1;
-    z = (int)(rest % L2);
-    t = (int)(rest / L2);
-    x = 2 * xh + ((y + z + t + a.out_par) & 1);
-  }
+  const int xh = (int)(j % hx);
+  long rest = j / hx;
+  const int y = (int)(rest % L1);
+  rest /= L1;
+  const int z = (int)(rest % L2);
+  const int t = (int)(rest / L2);
+  const int x = 2 * xh + ((y + z + t + a.out_par) & 1);
   const bool flip_f = a.bc_t < 0 && t + 1 == L3;  // forward t hop wraps
   const bool flip_b = a.bc_t < 0 && t == 0;       // backward t hop wraps
   constexpr int G = HopGroup<P>::G;
@@ -425,42 +578,21 @@ __device__ __forceinline__ void hop_sum(const HopArgs& a, long j0, long j, int s
       const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);  // 0,4,1,5,2,6,3,7
       const int mu = dir & 3;
       const bool fwd = dir < 4;
-      if constexpr (ROW) {
-        int yy = y, zz = z, tt = t;
-        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
-        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
-        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
-        const int nrow = (tt * L2 + zz) * L1 + yy;
-        const unsigned off = mu == 0 ? (fwd ? off_xp : off_xm) : off_own;
-        const unsigned char* base = reinterpret_cast<const unsigned char*>(a.in) + (size_t)nrow * row_bytes;
-        uint4 q[NCG];
-#pragma unroll
-        for (int cg = 0; cg < NCG; cg++)
-          q[cg] = *reinterpret_cast<const uint4*>(base + off + (size_t)cg * NS * 16);
-#pragma unroll
-        for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &psi[k][cg * P::CPB]);
-        if constexpr (P::SCALED) {
-          const unsigned so = mu == 0 ? (fwd ? soff_xp : soff_xm) : soff_own;
-          scl[k] = *reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(a.in_sc) +
-                                                   (size_t)nrow * srow_bytes + so);
-        } else {
-          scl[k] = R(1);
-        }
-      } else {
-        int xx = x, yy = y, zz = z, tt = t;
-        if (mu == 0) xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1);
-        if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
-        if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
-        if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
-        const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
-        if constexpr (P::SCALED) load_site_cached_raw<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k], scl[k]);
-        else load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
+      int xx = x, yy = y, zz = z, tt = t;
+      if (mu == 0) xx = fwd ? (x + 1 == L0 ? 0 : x + 1) : (x == 0 ? L0 - 1 : x - 1);
+      if (mu == 1) yy = fwd ? (y + 1 == L1 ? 0 : y + 1) : (y == 0 ? L1 - 1 : y - 1);
+      if (mu == 2) zz = fwd ? (z + 1 == L2 ? 0 : z + 1) : (z == 0 ? L2 - 1 : z - 1);
+      if (mu == 3) tt = fwd ? (t + 1 == L3 ? 0 : t + 1) : (t == 0 ? L3 - 1 : t - 1);
+      const long nj = (((long)tt * L2 + zz) * L1 + yy) * hx + (xx >> 1);
+      if constexpr (P::SCALED) load_site_cached_raw<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k], scl[k]);
+      else {
+        load_site_cached<P>(a.in, a.in_sc, nj, r, s, nrhs, NS, psi[k]);
+        scl[k] = R(1);
       }
     }
 #pragma unroll
     for (int k = 0; k < G; k++) {
       const int dir = ((g0 + k) >> 1) | (((g0 + k) & 1) << 2);
-      const bool fwd = dir < 4;
       if ((dir == 3 && flip_f) || (dir == 7 && flip_b)) {
         if constexpr (P::SCALED) {
           scl[k] = -scl[k];
@@ -469,28 +601,9 @@ __device__ __forceinline__ void hop_sum(const HopArgs& a, long j0, long j, int s
           for (int c = 0; c < 12; c++) psi[k][c] = {-psi[k][c].re, -psi[k][c].im};
         }
       }
-      // forward hop: (1 - gamma) for W, (1 + gamma) for W^dag; backward swapped
-      const bool minus = fwd != DAG;
-      if constexpr (P::SCALED) {
-        const R sc = scl[k];
-        switch (dir & 3) {
-          case 0: if (minus) hop_one_scaled<0, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<0, -1>(psi[k], sc, U + dir * 9, acc); break;
-          case 1: if (minus) hop_one_scaled<1, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<1, -1>(psi[k], sc, U + dir * 9, acc); break;
-          case 2: if (minus) hop_one_scaled<2, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<2, -1>(psi[k], sc, U + dir * 9, acc); break;
-          default: if (minus) hop_one_scaled<3, +1>(psi[k], sc, U + dir * 9, acc); else hop_one_scaled<3, -1>(psi[k], sc, U + dir * 9, acc); break;
-        }
-      } else {
-        switch (dir & 3) {
-          case 0: if (minus) hop_one<0, +1>(psi[k], U + dir * 9, acc); else hop_one<0, -1>(psi[k], U + dir * 9, acc); break;
-          case 1: if (minus) hop_one<1, +1>(psi[k], U + dir * 9, acc); else hop_one<1, -1>(psi[k], U + dir * 9, acc); break;
-          case 2: if (minus) hop_one<2, +1>(psi[k], U + dir * 9, acc); else hop_one<2, -1>(psi[k], U + dir * 9, acc); break;
-          default: if (minus) hop_one<3, +1>(psi[k], U + dir * 9, acc); else hop_one<3, -1>(psi[k], U + dir * 9, acc); break;
-        }
-      }
+      hop_dir<P, DAG>(dir, psi[k], scl[k], U, acc);
     }
   }
-#pragma unroll
-  for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
 }
 
 // minimum waves per SIMD the register allocation must allow (the fused FP32
@@ -566,8 +679,8 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   if (valid) {
     const cpx<R>* U = lnk + (size_t)sl * 8 * 9;
     // (row offsets are 32-bit: a row of a half field is at most 3 MB here)
-    if ((a.L[0] >> 1) % a.spb == 0 && a.L[0] <= 256) hop_sum<P, NS, DAG, true>(a, j0, j, sl, r, s, U, acc);
-    else hop_sum<P, NS, DAG, false>(a, j0, j, sl, r, s, U, acc);
+    if ((a.L[0] >> 1) % a.spb == 0 && a.L[0] <= 256) hop_sum_row<P, NS, DAG>(a, (int)j0, sl, r, s, U, acc);
+    else hop_sum<P, NS, DAG>(a, j, r, s, U, acc);
   }
   if constexpr (PLAIN) {
     if (valid) store_site<P, ODWF_NT_STORE>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
@@ -585,221 +698,6 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
 }
 
 
-// ---------------------------------------------------------------------------
-// t-sweep hopping kernel.  Block b owns the output sites of one x-row segment
-// (seg, y, z) for t in [t0, t0 + sweep) and walks them in t.  The input
-// spinor of the block's own column at t is carried from step to step in
-// registers: it is the x-hop input at step t (one of the two x neighbours of
-// every output site lies in the own column, the other in the adjacent lane,
-// exchanged through LDS), the +t neighbour at step t - 1 and, as its projected
-// half spinor, the -t neighbour at step t + 1.  Each input row of the column is
-// therefore read from memory once per sweep instead of three times; the y and
-// z neighbours are the own columns of concurrently running blocks and are
-// read while they are still in L2.  The epilogue of every step is the one of
-// the one-t-per-block kernel.
-// ---------------------------------------------------------------------------
-#ifndef ODWF_SWEEP_WAVES_PLAIN
-#define ODWF_SWEEP_WAVES_PLAIN 2
-#endif
-// minimum waves per SIMD of the t-sweep kernel (its column state costs registers)
-template <class P, bool PLAIN>
-struct SweepWaves {
-  static constexpr int W = sizeof(typename P::real) == 8 ? (PLAIN ? 2 : 1) : (PLAIN ? ODWF_SWEEP_WAVES_PLAIN : 2);
-};
-
-template <class P, int NS, bool DAG, bool PLAIN>
-__global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kernel(const HopArgs a) {
-  using R = typename P::real;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nrhs = a.nrhs;
-  const int inner = nrhs * NS;
-  const int tid = threadIdx.x;
-  const int sl = tid / inner;
-  const int lr = tid - sl * inner;
-  const int r = lr / NS;
-  const int s = lr - r * NS;
-  if (!gate_any(a.gate, a.gate_mode, nrhs)) {
-    // idle block: its partial-sum slots still have to read zero
-    if (a.partial && tid < nrhs) {
-      a.partial[(long)blockIdx.x * nrhs + tid] = 0.0;
-      for (int k = 1; k < a.sweep; k++)
-        a.partial[((long)gridDim.x + (long)blockIdx.x * (a.sweep - 1) + (k - 1)) * nrhs + tid] = 0.0;
-    }
-    return;
-  }
-  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
-  const int hx = L0 >> 1;
-  const int spb = a.spb;
-  const int nseg = hx / spb;
-
-  // block -> (segment, y, z, first t): XCD-aware ranges, (y, z) tiles, t chunks slowest
-  int lb = blockIdx.x;
-  if (a.xcd) {
-    const int q = a.nblocks >> 3, rem = a.nblocks & 7;
-    const int xc = lb & 7, k = lb >> 3;
-    lb = xc * q + min(xc, rem) + k;
-  }
-  const int ty = a.tile_y > 0 ? a.tile_y : 1, tz = a.tile_z > 0 ? a.tile_z : 1;
-  const int seg = lb % nseg;
-  lb /= nseg;
-  const int yi = lb % ty;
-  lb /= ty;
-  const int zi = lb % tz;
-  lb /= tz;
-  const int nty = L1 / ty, ntz = L2 / tz;
-  const int y = (lb % nty) * ty + yi;
-  lb /= nty;
-  const int z = (lb % ntz) * tz + zi;
-  lb /= ntz;
-  const int t0 = lb * a.sweep;
-
-  // padded threads have sl >= spb; gated-off right-hand sides do no work
-  const bool valid = sl < spb && gate_on(a.gate, a.gate_mode, r);
-  const int xh = seg * spb + sl;  // half-row index of this lane's output and own input column
-  constexpr int NSP = NS + 1;
-
-  // LDS: links, the x-exchange buffer (spb + 2 sites: the segment and one
-  // halo site on each side) aliased with the column buffer, kappa, reduction scratch
-  const size_t lnk_n = (size_t)spb * 8 * 9;
-  const int xstride = (spb + 2) * inner;  // per component
-  const size_t xch_n = (size_t)12 * xstride;
-  const size_t col_n = (size_t)spb * nrhs * 12 * NSP;
-  const size_t buf_n = PLAIN || xch_n > col_n ? xch_n : col_n;
-  cpx<R>* lnk = reinterpret_cast<cpx<R>*>(smem);
-  cpx<R>* buf = lnk + lnk_n;
-  const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
-  R* kap = reinterpret_cast<R*>(smem + region);
-  double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
-  const R* coef = reinterpret_cast<const R*>(a.coef);
-  if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
-
-  auto row = [&](int tt, int zz, int yy) { return (((long)tt * L2 + zz) * L1 + yy) * hx; };
-  // sign of the +t and -t hops: forward (1 - gamma_t) for W, (1 + gamma_t) for W^dag
-  constexpr int SIG_TF = DAG ? -1 : +1;
-  constexpr int SIG_TB = DAG ? +1 : -1;
-  const int yp = y + 1 == L1 ? 0 : y + 1, ym = y == 0 ? L1 - 1 : y - 1;
-  const int zp = z + 1 == L2 ? 0 : z + 1, zm = z == 0 ? L2 - 1 : z - 1;
-  const int xslot = (sl + 1) * inner + lr;  // this lane's column in the exchange buffer
-
-  // column state: cur = input at (xh, t); hm = projected -t term for the output at t
-  cpx<R> cur[12];
-  cpx<R> hm[6];
-  if (valid) {
-    load_site_row<P>(a.in, a.in_sc, row(t0, z, y), xh, r, s, nrhs, NS, cur);
-    cpx<R> pv[12];
-    load_site_row<P>(a.in, a.in_sc, row(t0 == 0 ? L3 - 1 : t0 - 1, z, y), xh, r, s, nrhs, NS, pv);
-    if (t0 == 0 && a.bc_t < 0) {
-#pragma unroll
-      for (int c = 0; c < 12; c++) pv[c] = {-pv[c].re, -pv[c].im};
-    }
-    project<3, SIG_TB>(pv, hm);
-  }
-  double nval = 0.0;
-
-#pragma unroll 1
-  for (int t = t0; t < t0 + a.sweep; t++) {
-    const long rt = row(t, z, y);
-    const long j0 = rt + (long)seg * spb;
-    const long j = j0 + sl;
-    // the output site sits at x = 2 xh + shift: the own column is its +x
-    // neighbour when shift = 0 (the -x one is the previous lane's column), and
-    // its -x neighbour when shift = 1 (the +x one is the next lane's column)
-    const int shift = (y + z + t + a.out_par) & 1;
-    __syncthreads();  // readers of the previous step's links and buffers are done
-    stage_links<P>(a.links, j0, spb, lnk);
-    if (sl < spb) {
-#pragma unroll
-      for (int c = 0; c < 12; c++) buf[(size_t)c * xstride + xslot] = cur[c];
-      // halo: the column beyond the segment edge on the side this step needs
-      const bool edge = shift ? sl == spb - 1 : sl == 0;
-      if (edge && gate_on(a.gate, a.gate_mode, r)) {
-        const int xo = shift ? (xh + 1 == hx ? 0 : xh + 1) : (xh == 0 ? hx - 1 : xh - 1);
-        cpx<R> o[12];
-        load_site_row<P>(a.in, a.in_sc, rt, xo, r, s, nrhs, NS, o);
-        const int hs = xslot + (shift ? inner : -inner);
-#pragma unroll
-        for (int c = 0; c < 12; c++) buf[(size_t)c * xstride + hs] = o[c];
-      }
-    }
-    __syncthreads();
-
-    cpx<R> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = {R(0), R(0)};
-    cpx<R> nxt[12];
-    if (valid) {
-      const cpx<R>* U = lnk + (size_t)sl * 8 * 9;
-      // terms summed in the order +x, -x, +y, -y, +z, -z, +t, -t, as in the
-      // one-t-per-block kernel, so that both round alike
-      {
-        cpx<R> o[12];
-        const int sp = xslot + (shift ? inner : 0), sm = xslot - (shift ? 0 : inner);
-#pragma unroll
-        for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + sp];
-        hop_one<0, DAG ? -1 : +1>(o, U + 0 * 9, acc);
-#pragma unroll
-        for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + sm];
-        hop_one<0, DAG ? +1 : -1>(o, U + 4 * 9, acc);
-      }
-      // y and z hops from the neighbouring columns, one direction pair per round
-#pragma unroll 1
-      for (int mu = 1; mu <= 2; mu++) {
-        cpx<R> pp[12], pm[12];
-        load_site_row<P>(a.in, a.in_sc, mu == 1 ? row(t, z, yp) : row(t, zp, y), xh, r, s, nrhs, NS, pp);
-        load_site_row<P>(a.in, a.in_sc, mu == 1 ? row(t, z, ym) : row(t, zm, y), xh, r, s, nrhs, NS, pm);
-        if (mu == 1) {
-          hop_one<1, DAG ? -1 : +1>(pp, U + 1 * 9, acc);
-          hop_one<1, DAG ? +1 : -1>(pm, U + 5 * 9, acc);
-        } else {
-          hop_one<2, DAG ? -1 : +1>(pp, U + 2 * 9, acc);
-          hop_one<2, DAG ? +1 : -1>(pm, U + 6 * 9, acc);
-        }
-      }
-      {  // +t: the next input of the own column
-        load_site_row<P>(a.in, a.in_sc, row(t + 1 == L3 ? 0 : t + 1, z, y), xh, r, s, nrhs, NS, nxt);
-        if (t + 1 == L3 && a.bc_t < 0) {
-#pragma unroll
-          for (int c = 0; c < 12; c++) nxt[c] = {-nxt[c].re, -nxt[c].im};
-        }
-        hop_one<3, SIG_TF>(nxt, U + 3 * 9, acc);
-      }
-      {  // -t: the projected input of the previous step
-        cpx<R> g[6];
-        su3_mul(U + 7 * 9, hm, g);
-        reconstruct<3, SIG_TB>(g, acc);
-      }
-#pragma unroll
-      for (int c = 0; c < 12; c++) acc[c] = cscale(R(-0.5), acc[c]);
-      // the -t term of the next output is this step's own input
-      cpx<R> o[12];
-#pragma unroll
-      for (int c = 0; c < 12; c++) o[c] = buf[(size_t)c * xstride + xslot];
-      project<3, SIG_TB>(o, hm);
-    }
-
-    if constexpr (PLAIN) {
-      if (valid) store_site<P>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
-    } else {
-      __syncthreads();  // the x-exchange buffer becomes the column buffer
-      nval += fused_tail<P, NS>(a, acc, valid, j, sl, r, s, spb, buf, coef, kap, X_LOAD);
-    }
-    if (valid) {
-#pragma unroll
-      for (int c = 0; c < 12; c++) cur[c] = nxt[c];
-    }
-  }
-
-  if (!PLAIN && a.partial) {
-    // one slot for the whole sweep, zeros in the slots of the other steps so
-    // that the partial array has the layout of the one-t-per-block kernel
-    block_reduce_rhs(valid ? nval : 0.0, NS, spb, nrhs, red, a.partial, blockIdx.x);
-    if (tid < nrhs) {
-      for (int k = 1; k < a.sweep; k++)
-        a.partial[((long)gridDim.x + (long)blockIdx.x * (a.sweep - 1) + (k - 1)) * nrhs + tid] = 0.0;
-    }
-  }
-}
-
 // extra LDS per block (plain / fused kernels): caps the blocks resident per CU
 #ifndef ODWF_HOP_SMEM_PAD
 #define ODWF_HOP_SMEM_PAD 0
@@ -808,12 +706,10 @@ __global__ void __launch_bounds__(256, (SweepWaves<P, PLAIN>::W)) hop_sweep_kern
 #define ODWF_HOP_SMEM_PAD_F 0
 #endif
 template <class P, int NS>
-static size_t hop_smem(int spb, int nrhs, int block, bool plain, bool sweep) {
+static size_t hop_smem(int spb, int nrhs, int block, bool plain) {
   using R = typename P::real;
   const size_t lnk_n = (size_t)spb * 8 * 9;
-  const size_t col_n = plain ? 0 : (size_t)spb * nrhs * 12 * (NS + 1);
-  const size_t xch_n = (size_t)12 * (spb + 2) * nrhs * NS;  // x-exchange buffer with halo
-  const size_t buf_n = sweep ? (xch_n > col_n ? xch_n : col_n) : col_n;
+  const size_t buf_n = plain ? 0 : (size_t)spb * nrhs * 12 * (NS + 1);
   const size_t region = (lnk_n + buf_n) * sizeof(cpx<R>);
   size_t off = (region + MAXRHS * sizeof(R) + 15) & ~size_t(15);
   return off + (size_t)(block + 16 * MAXRHS) * sizeof(double) +
@@ -828,24 +724,8 @@ static hipError_t launch_hop_t(HopArgs a, int dag, hipStream_t st) {
   const int block = (a.spb * inner + 63) & ~63;  // whole waves, <= 256
   const bool plain = a.prog_h.n == 0 && a.prog_o.n == 0 && a.xin == nullptr && a.partial == nullptr &&
                      a.c_h == 1.0;
-  const int hx = a.L[0] / 2;
-  const bool sweep = a.sweep > 0 && hx % a.spb == 0 && a.L[3] % a.sweep == 0 &&
-                     (a.tile_y <= 0 || a.L[1] % a.tile_y == 0) && (a.tile_z <= 0 || a.L[2] % a.tile_z == 0);
-  if (sweep) {
-    a.nblocks = (int)(a.h / a.spb / a.sweep);
-    const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain, true);
-    if (plain) {
-      if (dag) hipLaunchKernelGGL((hop_sweep_kernel<P, NS, true, true>), dim3(a.nblocks), dim3(block), sm, st, a);
-      else hipLaunchKernelGGL((hop_sweep_kernel<P, NS, false, true>), dim3(a.nblocks), dim3(block), sm, st, a);
-    } else {
-      if (dag) hipLaunchKernelGGL((hop_sweep_kernel<P, NS, true, false>), dim3(a.nblocks), dim3(block), sm, st, a);
-      else hipLaunchKernelGGL((hop_sweep_kernel<P, NS, false, false>), dim3(a.nblocks), dim3(block), sm, st, a);
-    }
-    return hipGetLastError();
-  }
-  a.sweep = 0;
   a.nblocks = (int)((a.h + a.spb - 1) / a.spb);
-  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain, false);
+  const size_t sm = hop_smem<P, NS>(a.spb, a.nrhs, block, plain);
   if (plain) {
     if (dag) hipLaunchKernelGGL((hop_kernel<P, NS, true, true>), dim3(a.nblocks), dim3(block), sm, st, a);
     else hipLaunchKernelGGL((hop_kernel<P, NS, false, true>), dim3(a.nblocks), dim3(block), sm, st, a);

@@ -113,9 +113,6 @@ struct HopArgs {
   // walking all tiles before the next chunk starts
   int xcd, tile_y, tile_z, tile_t, tile_x;
   int xcd_gy;  // xcd = 2: tiles of a lockstep group along y (1, 2, 4 or 8)
-  // t-sweep kernel: > 0 is the number of consecutive t each block walks for
-  // its (x-row segment, y, z) column; 0 selects the one-t-per-block kernel
-  int sweep;
   // gating: lanes of right-hand sides not selected by gate_mode do no work
   const CGScal* gate;
   int gate_mode;

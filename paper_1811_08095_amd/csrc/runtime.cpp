@@ -159,12 +159,6 @@ static void traversal(HopArgs& a, int Ns) {
       }
     }
   }
-  // t-sweep kernel: blocks walk sweep consecutive t of one column
-  a.sweep = 0;
-  if (const char* sw = getenv("ODWF_SWEEP")) {
-    const int n = atoi(sw);
-    if (n > 0 && hx % spb == 0 && a.L[3] % n == 0) a.sweep = n;
-  }
 }
 
 hipError_t hop(const OpCtx& c, int out_par, int dag, const HV& in, const HV* out, const HopOpt& o) {

@@ -6,9 +6,9 @@ Synthetic links (eps = 0.7, seed 0) and one Gaussian source are generated in
 HBM; for every storage precision the plain even-odd hop W_eo and the normal
 operator S_e^dag S_e (four fused hop launches) are applied after one warm-up,
 and the library's own HIP-event timing reports the average launch time and the
-algorithmic GB/s of the hop launches.  The block traversal and the t-sweep
-kernel follow the ODWF_TRAVERSAL, ODWF_XCD and ODWF_SWEEP environment
-variables, which are echoed in every output line.
+algorithmic GB/s of the hop launches.  The block traversal follows the
+ODWF_TRAVERSAL and ODWF_XCD environment variables, which are echoed in every
+output line.
 """
 import argparse
 import json
@@ -55,7 +55,7 @@ def main(argv=None):
             print(json.dumps({"dims": args.dims, "Ns": args.Ns,
                               "traversal": os.environ.get("ODWF_TRAVERSAL", "default"),
                               "xcd": os.environ.get("ODWF_XCD", "default"),
-                              "sweep": os.environ.get("ODWF_SWEEP", "0"), "prec": pname, "op": oname,
+                              "prec": pname, "op": oname,
                               "launches": n, "avg_ms": round(ms / n, 4),
                               "GBs": round(by / (ms * 1e-3) / 1e9, 1)}), flush=True)
     sol.close()
