@@ -52,6 +52,7 @@ PIN_CALLS = [
     (pins.test_hop_entries_are_parity_blocks_of_dense_wilson, {"dims": (4, 2, 2, 6), "bc_t": -1}),
     (pins.test_m5inv_entry_is_the_site_local_inverse, {}),
     (pins.test_normal_residual_against_dense_schur_from_pinned_blocks, {"bc_t": -1}),
+    (pins.test_5d_free_field_blocks_give_the_pauli_villars_ratio, {"mq": 0.5}),
     (fpins.test_force_is_the_derivative_of_the_bilinear, {"bc_t": -1}),
     (fpins.test_force_gauge_covariance, {}),
 ]

@@ -9,7 +9,7 @@ import pytest
 
 from dense_helpers import (dense_dw, dense_of, dense_op, gamma5_full, m5_full, random_su3)
 from oracle import oracle
-from oracle.zolotarev import omega_zolotarev, sign_approx_matrix
+from oracle.zolotarev import omega_zolotarev, sign_approx, sign_approx_matrix
 from paper_1811_08095_amd import synth
 
 M0 = 1.3  # §2: m0 = 1.3
@@ -346,3 +346,54 @@ def test_normal_residual_against_dense_schur_from_pinned_blocks(bc_t):
         got = oracle.normal_residual(U, f, yy.reshape(f.shape), M0, w, mu, bc_t)
         # rounding of N y (entries of order |f|) bounds the difference, not its size
         assert abs(got - expect) <= 1e-12, (got, expect)
+
+
+@pytest.mark.parametrize("mq", [0.01, 0.5])
+def test_5d_free_field_blocks_give_the_pauli_villars_ratio(mq):
+    """Unit links: the 5D operator maps a plane wave exp(i p.x) chi(s, spin) to
+    a plane wave of the same momentum, colour by colour, so it block-
+    diagonalises into 4 N_s x 4 N_s blocks D(p; mu) read off the oracle.  Per
+    momentum, §2 fixes det D(p; mu) / det D(p; 1) = det[(1 + mu)/2 + (1 - mu)/2
+    gamma5 S(H_w(p))], with H_w(p) = gamma5 D_w(p) and, on free fields,
+    H_w(p)^2 = lambda_p^2 (lambda_p^2 = (sum(1 - cos p) - m0)^2 + sum sin^2 p),
+    so S(H_w(p)) = S(lambda_p) H_w(p) / lambda_p with the Zolotarev S of the
+    weights (pinned separately by equioscillation).  Pins the 5D momentum-space
+    form: the s couplings, the mass term's corners and its chirality pairing."""
+    dims = (4, 2, 2, 4)
+    X, Y, Z, T = dims
+    U = synth.unit_gauge(dims)
+    Ns = 8
+    w = omega_zolotarev(LMIN, LMAX, Ns)
+    mu = mq / (2 * M0)
+    g = oracle.gammas()
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        n = [rng.integers(0, L) for L in dims]
+        p = np.array([2 * np.pi * n[0] / X, 2 * np.pi * n[1] / Y, 2 * np.pi * n[2] / Z,
+                      2 * np.pi * (n[3] + 0.5) / T])  # bc_t = -1
+        phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+
+        def block(m):
+            B = np.zeros((4 * Ns, 4 * Ns), np.complex128)
+            for col in range(4 * Ns):
+                for c in range(3):
+                    psi = np.zeros((Ns, T, Z, Y, X, 4, 3), np.complex128)
+                    psi[col // 4, ..., col % 4, c] = phase
+                    out = oracle.apply(oracle.OP_D, U, psi, M0, w, m, -1)
+                    # the image is the same plane wave in the same colour
+                    coef = (out * phase.conj()[None, ..., None, None]).mean(axis=(1, 2, 3, 4))
+                    rebuilt = coef[:, None, None, None, None, :, :] * phase[None, ..., None, None]
+                    assert np.abs(out - rebuilt).max() < 1e-12
+                    assert np.abs(np.delete(coef, c, axis=2)).max() < 1e-12
+                    B[:, col] = coef[:, :, c].reshape(4 * Ns)
+            return B
+
+        ratio = np.linalg.det(block(mu)) / np.linalg.det(block(1.0))
+        b = np.sum(1 - np.cos(p)) - M0
+        Dw = b * np.eye(4) + 1j * sum(np.sin(p[m]) * g[m] for m in range(4))
+        H = g[4] @ Dw
+        lam = np.sqrt(b * b + np.sum(np.sin(p) ** 2))
+        S = sign_approx(lam, w) * H / lam
+        expect = np.linalg.det(0.5 * (1 + mu) * np.eye(4) + 0.5 * (1 - mu) * g[4] @ S)
+        assert abs(ratio - expect) <= 1e-10 * abs(expect)
