@@ -17,9 +17,11 @@
 // neighbour.  The 8 links of the block's sites are staged once in LDS and
 // shared by all nrhs * Ns lanes of a site (links are stored per output parity
 // as [site][8][...] with directions 0-3 forward U_mu(x) and 4-7 backward
-// U_mu(x - mu)^dag).  Fifth-dimension programs run in LDS on columns
-// (site, r, colour-spin component) of Ns values.  No MFMA: the stencil is a
-// string of 3x3 complex mat-vecs and is bound by HBM bandwidth.
+// U_mu(x - mu)^dag).  Fifth-dimension programs run across the 16 lanes of a
+// DPP row for FP32 arithmetic at Ns = 16 (one slice per lane), otherwise on LDS
+// columns (site, r, colour-spin component) of Ns values.  No MFMA: the stencil
+// is a string of 3x3 complex mat-vecs; its time is set by the traffic between
+// the L2 caches and memory (FP32, FP64) or by VALU issue (FP16, BF16 storage).
 #include <type_traits>
 
 #include "dev_common.h"
