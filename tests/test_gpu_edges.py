@@ -83,3 +83,24 @@ def test_error_paths():
     out = sol.apply(odwf.OP_D, psi, [0.1], prec=odwf.FP64).cpu().numpy()[0]
     ref = oracle.apply(oracle.OP_D, U, psi.cpu().numpy()[0], M0, w, 0.1 / (2 * M0), -1)
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [(odwf.FP64, 1e-12), (odwf.FP32, 1e-5), (odwf.FP16S, 4e-3)],
+                         ids=["fp64", "fp32", "fp16s"])
+def test_apply_widest_launch_ns16(prec, bound):
+    """N_s = 16 takes at most 16 right-hand sides per launch: a block is then
+    one site with 16 x 16 lanes (the fifth-dimension lane programs run on 16
+    DPP rows of one block).  17 right-hand sides with their own masses are
+    split 16 + 1; each matches the oracle (FP64 to 1e-12, reduced precisions
+    within their stated bounds)."""
+    import torch
+    dims, Ns, n = (4, 2, 2, 4), 16, 17
+    U, w, lat, sol = _mk(dims, Ns, seed=5, eps=0.7)
+    psi = synth.make_source(dims, Ns, n, 3500)
+    masses = list(np.linspace(0.0025, 0.5, n))
+    for op in (odwf.OP_HOP_EO, odwf.OP_D, odwf.OP_SCHUR_NORMAL):
+        out = sol.apply(op, torch.from_numpy(psi).cuda(), masses, prec=prec).cpu().numpy()
+        for r in range(n):
+            ref = oracle.apply(op, U, psi[r], M0, w, masses[r] / (2 * M0), -1)
+            err = np.linalg.norm(out[r] - ref) / np.linalg.norm(ref)
+            assert err <= bound, (op, r, err)
