@@ -584,13 +584,24 @@ __device__ __forceinline__ void lane_solve(cpx<float> (&y)[12], int c0, float a)
   }
 }
 
+// the program loop unrolled over its four op slots (1, default), so the
+// coefficient reads of a step can be issued before the previous step ends
+#ifndef ODWF_M5_UNROLL
+#define ODWF_M5_UNROLL 1
+#endif
 template <int NS>
 __device__ __forceinline__ void m5_run_lanes(const M5Prog& prog, cpx<float> (&y)[12],
                                              const float* __restrict__ cf, float kappa, int s) {
   static_assert(NS == 16, "one DPP row per column");
   const int up = s, um = NS - 1 - s;  // chirality-local slice index, chirality + and -
   const float* cfm = cf + NCOEF * NS;
+#if ODWF_M5_UNROLL
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(prog.op) / sizeof(prog.op[0])); k++) {
+    if (k >= prog.n) break;
+#else
   for (int k = 0; k < prog.n; k++) {
+#endif
     const M5Op op = prog.op[k];
     const float dp = cf[op.d * NS + up], dm = cfm[op.d * NS + um];
     float ep = cf[op.e * NS + up], em = cfm[op.e * NS + um];

@@ -608,6 +608,11 @@ __device__ __forceinline__ void hop_sum(const HopArgs& a, long j, int r, int s,
   }
 }
 
+// fifth-dimension coefficients of the lane-parallel programs staged in LDS
+// (1, default) or read from global memory (0)
+#ifndef ODWF_LDS_COEF
+#define ODWF_LDS_COEF 1
+#endif
 // minimum waves per SIMD the register allocation must allow (the fused FP32
 // kernels fit four when their column programs run across lanes)
 #ifndef ODWF_HOP_WAVES32
@@ -654,6 +659,11 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   double* red = reinterpret_cast<double*>(smem + ((region + MAXRHS * sizeof(R) + 15) & ~size_t(15)));
   const R* coef = reinterpret_cast<const R*>(a.coef);
   if (!PLAIN && tid < nrhs) kap[tid] = (R)a.kappa[tid];
+  // the lane-parallel programs read their coefficients at every step: from a
+  // copy in the (otherwise unused) column buffer those are LDS reads
+  R* coef_lds = reinterpret_cast<R*>(buf);
+  if constexpr (!PLAIN && LanePass<R, NS>::on && ODWF_LDS_COEF)
+    for (int i = tid; i < 2 * NCOEF * NS; i += blockDim.x) coef_lds[i] = coef[i];
   stage_links<P>(a.links, j0, nsb, lnk);
 
   cpx<R> xv[12];
@@ -694,7 +704,8 @@ __global__ void __launch_bounds__(256, (HopWaves<P, NS, PLAIN>::W)) hop_kernel(c
   // the empty asm stops the compiler from reusing the value computed earlier
   int slr = sl;
   asm volatile("" : "+v"(slr));
-  const double nval = fused_tail<P, NS>(a, acc, valid, j0 + slr, sl, r, s, nsb, buf, coef, kap,
+  const double nval = fused_tail<P, NS>(a, acc, valid, j0 + slr, sl, r, s, nsb, buf,
+                                        (LanePass<R, NS>::on && ODWF_LDS_COEF) ? coef_lds : coef, kap,
                                         x_first ? X_LDS : X_LOAD);
   if (a.partial) block_reduce_rhs(valid ? nval : 0.0, NS, a.spb, nrhs, red, a.partial, blockIdx.x);
 }
