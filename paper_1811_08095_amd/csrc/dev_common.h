@@ -83,6 +83,11 @@ struct SPB16 {
   static constexpr int BYTES = 4;
 };
 
+// BF16 stores through the hardware conversion (1, default) or the integer
+// rounding of f_to_bf16 (0); both round to nearest even
+#ifndef ODWF_HW_BF16_CVT
+#define ODWF_HW_BF16_CVT 1
+#endif
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 __device__ __forceinline__ uint16_t f_to_bf16(float f) {
   // round to nearest even; inputs are finite and bounded by 1 after scaling
@@ -153,8 +158,17 @@ template <>
 __device__ __forceinline__ uint4 pack_chunk<SPB16>(const cpx<float>* v, float inv) {
   uint32_t w[4];
 #pragma unroll
-  for (int k = 0; k < 4; k++)
+  for (int k = 0; k < 4; k++) {
+#if ODWF_HW_BF16_CVT
+    // one v_cvt_pk_bf16_f32 per complex (gfx950): round to nearest even, as f_to_bf16
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const f32x2 f = {v[k].re * inv, v[k].im * inv};
+    w[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+#else
     w[k] = (uint32_t)f_to_bf16(v[k].re * inv) | ((uint32_t)f_to_bf16(v[k].im * inv) << 16);
+#endif
+  }
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 

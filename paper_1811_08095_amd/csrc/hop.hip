@@ -98,6 +98,12 @@ __device__ __forceinline__ void stage_links(const void* links, long j0, int nsb,
   }
 }
 
+// neighbour scales of the FP16S/BF16S formats folded into the accumulating
+// fma (1, default) or multiplied into the link product first (0)
+#ifndef ODWF_SCALE_IN_FMA
+#define ODWF_SCALE_IN_FMA 1
+#endif
+
 // acc += [g; -SIG B^dag g]; (B^dag g)_b = conj(f_{p_b}) g_{p_b}
 template <int MU, int SIG, class R>
 __device__ __forceinline__ void reconstruct(const cpx<R> (&g)[6], cpx<R> (&acc)[12]) {
@@ -119,6 +125,26 @@ __device__ __forceinline__ void reconstruct(const cpx<R> (&g)[6], cpx<R> (&acc)[
       acc[6 + c] = cadd(acc[6 + c], l0);
       acc[9 + c] = cadd(acc[9 + c], l1);
     }
+  }
+}
+
+// the same with every term scaled by sc, the per-site scale of a neighbour
+// stored with one: acc += sc [g; -SIG B^dag g], each real one fma
+template <int MU, int SIG>
+__device__ __forceinline__ void reconstruct_scaled(const cpx<float> (&g)[6], float sc, cpx<float> (&acc)[12]) {
+  using B = GammaB<MU>;
+  constexpr int q0 = B::p0, q1 = B::p1;
+  constexpr int fq0 = (q0 == 0) ? B::f0 : B::f1;
+  constexpr int fq1 = (q1 == 0) ? B::f0 : B::f1;
+  const float sl = SIG > 0 ? -sc : sc;  // the lower components enter with -SIG
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    acc[c] = {fmaf(sc, g[c].re, acc[c].re), fmaf(sc, g[c].im, acc[c].im)};
+    acc[3 + c] = {fmaf(sc, g[3 + c].re, acc[3 + c].re), fmaf(sc, g[3 + c].im, acc[3 + c].im)};
+    const cpx<float> l0 = mulf<ConjCode<fq0>::v>(g[q0 * 3 + c]);
+    const cpx<float> l1 = mulf<ConjCode<fq1>::v>(g[q1 * 3 + c]);
+    acc[6 + c] = {fmaf(sl, l0.re, acc[6 + c].re), fmaf(sl, l0.im, acc[6 + c].im)};
+    acc[9 + c] = {fmaf(sl, l1.re, acc[9 + c].re), fmaf(sl, l1.im, acc[9 + c].im)};
   }
 }
 
@@ -149,17 +175,21 @@ __device__ __forceinline__ void hop_one(const cpx<R> (&psi)[12], const cpx<R>* U
 }
 
 // the same hop for a neighbour stored with a per-site scale: the projection and
-// the link product are linear, so the scale multiplies the 6 numbers of g
-// instead of the 12 of the spinor
+// the link product are linear, so the scale enters only where the terms are
+// accumulated (one fma per real instead of a product and a sum)
 template <int MU, int SIG, class R>
 __device__ __forceinline__ void hop_one_scaled(const cpx<R> (&psi)[12], R sc, const cpx<R>* U,
                                                cpx<R> (&acc)[12]) {
   cpx<R> h[6], g[6];
   project<MU, SIG>(psi, h);
   su3_mul(U, h, g);
+  if constexpr (ODWF_SCALE_IN_FMA && sizeof(R) == 4) {
+    reconstruct_scaled<MU, SIG>(g, sc, acc);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
-  reconstruct<MU, SIG>(g, acc);
+    for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
+    reconstruct<MU, SIG>(g, acc);
+  }
 }
 
 // first site of this block under the configured traversal
@@ -393,9 +423,13 @@ __device__ __forceinline__ void hop_one_h16(const uint32_t (&w)[12], float sc, f
     h[3 + c] = proj_h16<B::f1, SIG>(w[3 + c], w[(2 + B::p1) * 3 + c], one);
   }
   su3_mul(U, h, g);
+  if constexpr (ODWF_SCALE_IN_FMA) {
+    reconstruct_scaled<MU, SIG>(g, sc, acc);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
-  reconstruct<MU, SIG>(g, acc);
+    for (int k = 0; k < 6; k++) g[k] = cscale(sc, g[k]);
+    reconstruct<MU, SIG>(g, acc);
+  }
 }
 template <bool DAG>
 __device__ __forceinline__ void hop_dir_h16(int dir, const uint32_t (&w)[12], float sc, float one,
