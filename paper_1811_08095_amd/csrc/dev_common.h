@@ -179,8 +179,9 @@ struct HalfView {
   const float* __restrict__ scale;
 };
 
-// load the 12 components of 5D site (j, r, s)
-template <class P>
+// load the 12 components of 5D site (j, r, s); NT = 1: nontemporal loads
+// (a stream read once, which should not displace re-used rows from L2)
+template <class P, int NT = 0>
 __device__ __forceinline__ void load_site(const void* base, const float* scale, long j, int r, int s,
                                           int nrhs, int Ns, cpx<typename P::real> (&v)[12]) {
   constexpr int NCG = 12 / P::CPB;
@@ -188,7 +189,15 @@ __device__ __forceinline__ void load_site(const void* base, const float* scale, 
   const long off = ((j * nrhs + r) * NCG) * Ns + s;
   uint4 q[NCG];
 #pragma unroll
-  for (int cg = 0; cg < NCG; cg++) q[cg] = b[off + cg * Ns];
+  for (int cg = 0; cg < NCG; cg++) {
+    if constexpr (NT) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(b + off + cg * Ns));
+      q[cg] = make_uint4(w.x, w.y, w.z, w.w);
+    } else {
+      q[cg] = b[off + cg * Ns];
+    }
+  }
 #pragma unroll
   for (int cg = 0; cg < NCG; cg++) unpack_chunk<P>(q[cg], &v[cg * P::CPB]);
   if constexpr (P::SCALED) {

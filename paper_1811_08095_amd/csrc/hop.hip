@@ -285,6 +285,13 @@ struct HopGroup {
   static constexpr int G = sizeof(typename P::real) == 8 ? ODWF_HOP_GROUP64 : ODWF_HOP_GROUP32;
 };
 
+// the fused epilogue's own-site streams (x term, CG residual, output) are read
+// or written once per launch: nontemporal (1, default), so that they do not
+// displace the neighbour rows the hop re-reads from L2; 0: plain accesses
+#ifndef ODWF_NT_FUSED
+#define ODWF_NT_FUSED 1
+#endif
+
 // x term of the fused epilogue: already transformed in the column buffer, or
 // loaded here (and transformed here when it has a fifth-dimension program)
 enum XMode { X_LDS = 1, X_LOAD = 2 };
@@ -337,11 +344,11 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
         for (int c = 0; c < 12; c++) xv[c] = b[c * NSP];
       }
     } else {
-      if (valid) load_site<P>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
+      if (valid) load_site<P, ODWF_NT_FUSED>(a.xin, a.xin_sc, j, r, s, nrhs, NS, xv);
       if constexpr (LanePass<R, NS>::on && !P::SCALED) {
         // the CG residual travels with the x term: one memory round trip fewer
         if (cg_update) {
-          load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+          load_site<P, ODWF_NT_FUSED>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
           r_loaded = true;
         }
       }
@@ -378,19 +385,19 @@ __device__ __forceinline__ double fused_tail(const HopArgs& a, cpx<typename P::r
     if (cg_update) {
       const R al = (R)a.scal[r].alpha;
       {  // r -= alpha N p, |r|^2
-        if (!r_loaded) load_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+        if (!r_loaded) load_site<P, ODWF_NT_FUSED>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
 #pragma unroll
         for (int c = 0; c < 12; c++) {
           rv[c] = csub(rv[c], cscale(al, acc[c]));
           nval += (double)cnorm2(rv[c]);
         }
-        store_site<P>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
+        store_site<P, ODWF_NT_FUSED>(a.cg_r, a.cg_r_sc, j, r, s, nrhs, NS, rv);
       }
       // x += alpha p runs in the vector step after beta (vec_cg_step_kernel),
       // which reads p there anyway
     }
   } else if (valid && a.out) {
-    store_site<P, ODWF_NT_STORE>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
+    store_site<P, ODWF_NT_FUSED>(a.out, a.out_sc, j, r, s, nrhs, NS, acc);
   }
 
   return nval;
